@@ -1,0 +1,198 @@
+#!/usr/bin/env python3
+"""Throughput of the GRMHD zone update on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--precision fp64|mixed] [--recon mc|weno5]
+
+Workload (default): the Fishbone-Moncrief torus in Kerr (a = 0.9375, r_in = 6,
+r_max = 12, gamma = 13/9) on a 288 x 128 x 128 funky-MKS grid to r = 1000,
+single-loop field at beta = 100, seeded 4 % noise on u; MC reconstruction,
+LLF fluxes, Flux-CT, predictor-corrector, FP64. Synthetic initial data from
+``problems.fm_torus``; the state is resident in HBM before timing starts.
+
+A step is one full predictor-corrector cycle of every zone, including the
+Courant step read back each step (dt <- min(dt_next, 1.3 dt)). The metric is
+zone-cycles per second: interior zones x steps / wall seconds over the timed
+steps (bracketed by device synchronisation). Kernel durations over the same
+timed region come from HIP events the library records on its stream; the
+dominant kernel's algorithmic bytes per launch over its mean duration give the
+roofline fraction against 8 TB/s. The oracle (NumPy FP64, one core) is timed on
+a bounded sample of the same workload.
+
+Prints one JSON line on stdout.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+HBM_PEAK = 8.0e12          # bytes/s, MI355X HBM3E
+FP64_PEAK = 78.6e12        # flop/s, MI355X FP64 vector
+NG = 3
+
+
+def algorithmic_bytes(kernel, prm, mixed):
+    """Bytes one launch must move at minimum: every input value read once and
+    every output written once (stencil re-reads are cache traffic, not algorithm).
+    """
+    n1, n2, n3 = prm["n1"], prm["n2"], prm["n3"]
+    fb = 4 if mixed else 8
+    recon_reach = 3 if prm["recon"] == 1 else 2          # zones below / above+1 a face
+    if kernel in ("sweep1", "sweep2", "sweep3"):
+        d = int(kernel[-1])
+        n = [n1, n2, n3]
+        faces = 1
+        cells = 1
+        for e in range(3):
+            if e == d - 1:
+                faces *= n[e] + 1
+                cells *= n[e] + 2 * recon_reach
+            else:
+                faces *= n[e] + 2
+                cells *= n[e] + 2
+        geo = 22 * fb * (n1 + 2) * (n2 + 2)
+        return 64 * cells + 8 * fb * faces + geo
+    if kernel == "update":
+        zones = n1 * n2 * n3
+        # 7 flux components per direction (5 hydro + 2 transverse B), P_base, P_s
+        # read, P_out written, one flag byte; the 2D centre table once
+        return zones * (21 * fb + 64 + 64 + 64 + 1) + 64 * 8 * n1 * n2
+    raise KeyError(kernel)
+
+
+def cpu_baseline(prm_full, nslabs=8):
+    """The oracle on the same torus grid with nslabs x3 slabs, one step."""
+    import numpy as np
+    import oracle
+    import problems
+    prm, P0 = problems.fm_torus(n1=prm_full["n1"], n2=prm_full["n2"], n3=nslabs,
+                                recon=prm_full["recon"])
+    g = oracle.Grid(prm)
+    dt = 0.005
+    t0 = time.perf_counter()
+    oracle.step(P0, g, dt)
+    secs = time.perf_counter() - t0
+    zones = prm["n1"] * prm["n2"] * prm["n3"]
+    return {
+        "value": zones / secs,
+        "unit": "zone-cycles/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"1 FP64 step of the {prm['n1']}x{prm['n2']} FMKS torus grid with {nslabs} x3 slabs "
+                   f"({zones} zones, same per-zone work as the benchmark grid) in {secs:.1f} s; "
+                   "NumPy element-wise, single thread"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--recon", choices=["mc", "weno5"], default="mc")
+    ap.add_argument("--grid", type=int, nargs=3, default=[288, 128, 128])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="also run one plain device copy of this size (for counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build runs the zone update on a single device "
+              "(multi-GPU block decomposition is a design note only). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import problems
+    import paper_2110_10191_amd as g
+
+    recon = problems.RECON_MC if args.recon == "mc" else problems.RECON_WENO5
+    mixed = args.precision == "mixed"
+    n1, n2, n3 = args.grid
+    t_gen = time.perf_counter()
+    prm, P0 = problems.fm_torus(n1=n1, n2=n2, n3=n3, recon=recon,
+                                precision=problems.MIXED if mixed else problems.FP64)
+    print(f"[bench] initial data {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    sim = g.Sim(prm, device=dev)
+    P = sim.to_device(P0)
+    torch.cuda.synchronize()
+
+    dt = sim.get_dt(P)
+    for _ in range(args.warmup):
+        dt = min(sim.step(P, dt), 1.3 * dt)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
+
+    g.grmhd_profile(sim.ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dt = min(sim.step(P, dt), 1.3 * dt)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    g.grmhd_profile(sim.ctx, False)
+
+    kernels = {}
+    for name in g.KERNELS:
+        ms, n = g.grmhd_profile_read(sim.ctx, name)
+        kernels[name] = (ms, n)
+    fails = sim.step_failures()
+    divb = sim.divb(P)
+    zones = n1 * n2 * n3
+    value = zones * args.steps / secs
+    print("[bench] kernel ms/launch: " + ", ".join(
+        f"{k} {ms / max(n, 1):.3f}" for k, (ms, n) in kernels.items()), file=sys.stderr, flush=True)
+
+    dom = max(("sweep1", "sweep2", "sweep3", "update"), key=lambda k: kernels[k][0])
+    ms, n = kernels[dom]
+    per_launch = algorithmic_bytes(dom, prm, mixed)
+    achieved = per_launch / (ms / n / 1e3)
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK, "traffic": None, "kernel": dom,
+                "algorithmic_bytes_per_launch": per_launch, "mean_launch_ms": ms / n}
+
+    if args.copy_calibration_gib > 0:
+        nel = int(args.copy_calibration_gib * 2 ** 30) // 8
+        a = torch.ones(nel, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    out = {
+        "metric": "zone-cycles/s per GPU + % HBM roofline; batched-serving p50/p99 job latency",
+        "value": value,
+        "unit": "zone-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": secs / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if not mixed else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"fm_torus_{n1}x{n2}x{n3}_{args.recon}_{args.precision}",
+                   "grid": [n1, n2, n3], "a": prm["a"], "recon": args.recon,
+                   "precision": args.precision, "coords": "fmks", "r_out": 1000.0},
+        "roofline": roofline,
+        "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kernels.items()},
+        "checks": {"max_divb": divb, "failed_inversions_last_step": fails, "dt": dt},
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prm)
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

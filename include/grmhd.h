@@ -1,0 +1,163 @@
+/*
+ * grmhd.h -- C ABI of an MI355X (gfx950) library that advances ideal
+ * general-relativistic MHD in a fixed stationary spacetime by the HARM
+ * conservative finite-volume scheme that iharm3D implements.
+ *
+ * What the calls compute (the problem as the paper states it):
+ *   - ideal GRMHD on a logically Cartesian mesh in arbitrary coordinates of a
+ *     stationary metric whose line element is analytic (Functionality section;
+ *     Implementation Notes: metric quantities evaluated numerically);
+ *   - units GM = c = 1 (Implementation Notes);
+ *   - conserved variables stepped in time and inverted to primitives by the
+ *     1D_W scheme (Implementation Notes, after Noble et al. 2006);
+ *   - Flux-CT transport of the magnetic field (Implementation Notes, after
+ *     Toth 2000);
+ *   - the density / energy / magnetisation / Lorentz-factor bounds of the
+ *     Implementation Notes, applied after every substep.
+ *
+ * Data layout. A state (primitive P or conserved U) is one float64 array
+ *   [8][n3 + 6][n2 + 6][n1p],   n1p = n1 + 6 rounded up to a multiple of 8,
+ * x1 fastest, 3 ghost layers on each side of each direction; interior zone
+ * (i, j, k) sits at element ((v*(n3+6) + k+3)*(n2+6) + j+3)*n1p + i+3.
+ * grmhd_state_layout() returns the shape and strides. Variables, in order:
+ *   P: rho, u (internal energy density), u~1, u~2, u~3 (velocity relative to
+ *      the normal observer, code coordinates), B1, B2, B3;
+ *   U: sqrt(-g) (rho u^t, T^t_t + rho u^t, T^t_1, T^t_2, T^t_3, B1, B2, B3).
+ * Elements in the x1 alignment padding (i >= n1 + 3) are never read.
+ *
+ * Ownership and streams. The caller owns every state buffer: device memory on
+ * the device current at grmhd_init, sized per grmhd_state_layout. The library
+ * owns its geometry tables and scratch from grmhd_init until grmhd_free and
+ * keeps no caller pointer after a call returns. All work is enqueued on the
+ * stream given to grmhd_init; a call that returns a host scalar (dt, dt_next,
+ * n_fail, max_divb) synchronises that stream, every other call is
+ * asynchronous. Calls on one context must not overlap from several host
+ * threads.
+ *
+ * Errors. Every call returns GRMHD_OK (0) or a negative grmhd_status and
+ * never throws; grmhd_last_error(ctx) gives a message for the last failure on
+ * that context. Inversion failures are not errors: they are flagged per zone
+ * and repaired by the fixup (the bounds exist "to avoid catastrophic
+ * failures", Implementation Notes).
+ */
+#ifndef GRMHD_H
+#define GRMHD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GRMHD_OK = 0,
+  GRMHD_EINVAL = -1,       /* bad argument: null pointer, bad size or enum */
+  GRMHD_ENOMEM = -2,       /* device allocation failed */
+  GRMHD_EDEVICE = -3,      /* HIP runtime / kernel launch error, or no device */
+  GRMHD_EUNSUPPORTED = -4, /* valid but not implemented combination */
+  GRMHD_ESTATE = -5        /* a non-finite value appeared in the evolved state */
+} grmhd_status;
+
+enum { GRMHD_MINKOWSKI_CART = 0, GRMHD_KERR_MKS = 1, GRMHD_KERR_FMKS = 2 };
+enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1 };
+enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 };
+enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2, GRMHD_BC_DIRICHLET = 3 };
+enum { GRMHD_OPT_FLOORS = 1, GRMHD_OPT_FIXUP = 2 };
+
+#define GRMHD_NG 3
+#define GRMHD_NVAR 8
+
+/* One problem. Code coordinates:
+ *   MINKOWSKI_CART: Cartesian, metric diag(-1, 1, 1, 1);
+ *   KERR_MKS:  Kerr-Schild with r = exp(x1), theta = pi x2 + (1-hslope)/2 sin(2 pi x2),
+ *              phi = x3;
+ *   KERR_FMKS: as MKS, with theta blended towards the polynomial
+ *              theta_J = N y (1 + (y/poly_xt)^poly_alpha/(poly_alpha+1)) + pi/2,
+ *              y = 2 x2 - 1, by exp(-mks_smooth (x1 - x1min)).
+ * Zone centres sit at x_d = xdmin + (i + 1/2) (xdmax - xdmin)/nd.
+ * bc[d][side]: boundary type of direction d (0 = x1) at its lower (0) / upper (1)
+ * edge; PERIODIC on both sides or neither; OUTFLOW only in x1; POLAR only in
+ * x2; DIRICHLET keeps the ghost values the caller stored in the state.
+ * floors: 1 applies the bounds (needs a Kerr metric: they use r). */
+typedef struct grmhd_problem {
+  int32_t n1, n2, n3;
+  int32_t coords;
+  double a, gam, cfl;
+  double x1min, x1max, x2min, x2max, x3min, x3max;
+  double hslope, poly_xt, poly_alpha, mks_smooth;
+  int32_t recon;
+  int32_t precision;
+  int32_t bc[3][2];
+  int32_t floors;
+  double rho_fl, u_fl, sigma_max, beta_min, uorho_max, gamma_max;
+} grmhd_problem;
+
+typedef struct grmhd_ctx grmhd_ctx;
+
+/* Validate the problem, build the geometry tables on the device (metric,
+ * inverse, sqrt(-g), lapse at zone centres and faces; connection at centres by
+ * centred differences) and allocate scratch. hip_stream: a hipStream_t, or NULL
+ * for the null stream. Errors: EINVAL (bad problem), ENOMEM, EDEVICE. */
+int grmhd_init(const grmhd_problem *p, void *hip_stream, grmhd_ctx **out);
+
+/* Release everything the context owns. NULL is accepted. */
+int grmhd_free(grmhd_ctx *ctx);
+
+/* shape = {8, n3+6, n2+6, n1p}, strides in elements, and the element offset
+ * of interior zone (0,0,0) of variable 0. */
+int grmhd_state_layout(const grmhd_ctx *ctx, int64_t shape[4], int64_t strides[4],
+                       int64_t *interior_offset);
+
+/* Conserved variables of the interior zones of P (ghosts of U are not
+ * written). Functionality / Implementation Notes: U(P) is the analytic map. */
+int grmhd_prim_to_cons(grmhd_ctx *ctx, const double *P, double *U);
+
+/* 1D_W inversion of the interior zones (Implementation Notes). P is the
+ * Newton guess on entry and the result on exit. opts: GRMHD_OPT_FLOORS applies
+ * the bounds (if the problem has floors), GRMHD_OPT_FIXUP repairs failed zones
+ * from their neighbours. flags (nullable, same zone layout as one variable of
+ * a state, int8): 1 where the inversion failed, 0 elsewhere (interior only).
+ * n_fail (nullable, host): number of failed zones; synchronises. */
+int grmhd_cons_to_prim(grmhd_ctx *ctx, const double *U, double *P, int8_t *flags,
+                       int32_t opts, int64_t *n_fail);
+
+/* Courant step of state P: dt = cfl / sum_d (max_faces ctop_d / dx_d) with
+ * ctop the LLF signal speed at each face. Refills the ghost zones of P.
+ * dt (host) is written; synchronises. */
+int grmhd_get_dt(grmhd_ctx *ctx, double *P, double *dt);
+
+/* One second-order predictor-corrector step of size dt, in place on P
+ * (ghosts refilled). dt_next (nullable, host): the Courant step from the
+ * corrector's signal speeds; synchronises when given. Returns GRMHD_ESTATE if
+ * a non-finite signal speed appeared (only checked when dt_next is given). */
+int grmhd_step(grmhd_ctx *ctx, double *P, double dt, double *dt_next);
+
+/* max |div B| over cell corners, with div B the corner-centred divergence of
+ * sqrt(-g) B (the quantity Flux-CT keeps at round-off, Implementation Notes).
+ * Corners on non-periodic boundaries are excluded. Reads interior zones only.
+ * max_divb (host) is written; synchronises. */
+int grmhd_divb(grmhd_ctx *ctx, const double *P, double *max_divb);
+
+/* Failed-inversion count of the last grmhd_step (both substeps); synchronises. */
+int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
+
+/* Kernel timing for measurement. grmhd_profile(ctx, 1) clears the record and
+ * starts bracketing every kernel launch of grmhd_step with HIP events on the
+ * context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
+ * one kernel class, the summed device time in ms and the launch count since
+ * the last clear; synchronises. Timing adds two event records per launch. */
+enum {
+  GRMHD_K_GHOSTS = 0, GRMHD_K_SWEEP1 = 1, GRMHD_K_SWEEP2 = 2, GRMHD_K_SWEEP3 = 3,
+  GRMHD_K_UPDATE = 4, GRMHD_K_FIXUP = 5, GRMHD_K_COUNT = 6
+};
+int grmhd_profile(grmhd_ctx *ctx, int32_t enable);
+int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+const char *grmhd_strerror(int status);
+const char *grmhd_last_error(const grmhd_ctx *ctx);
+int grmhd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRMHD_H */

@@ -1,0 +1,21 @@
+"""MI355X (gfx950) GRMHD zone-update library: thin Python binding of libgrmhd.so.
+
+Every step of the method runs in the HIP kernels of ``libgrmhd.so``; this
+module only marshals arguments (problem struct, device pointers from torch
+tensors, the current HIP stream). The functions carry the C ABI's names
+(``grmhd_init``, ``grmhd_prim_to_cons``, ``grmhd_cons_to_prim``,
+``grmhd_get_dt``, ``grmhd_step``, ``grmhd_divb``, ...); ``Sim`` is a small
+convenience wrapper around them.
+
+Importing never falls back to anything: if the library is missing the import
+raises, and every call raises ``GrmhdError`` on a non-zero status.
+"""
+
+from ._binding import (  # noqa: F401
+    GrmhdError, Problem, LIB_PATH, lib, NG, NVAR,
+    GRMHD_OK, GRMHD_EINVAL, GRMHD_ENOMEM, GRMHD_EDEVICE, GRMHD_EUNSUPPORTED, GRMHD_ESTATE,
+    GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP, EXPORTED,
+    grmhd_init, grmhd_free, grmhd_state_layout, grmhd_prim_to_cons, grmhd_cons_to_prim,
+    grmhd_get_dt, grmhd_step, grmhd_divb, grmhd_step_failures, grmhd_strerror,
+    grmhd_last_error, grmhd_version, grmhd_profile, grmhd_profile_read, KERNELS, Sim,
+)

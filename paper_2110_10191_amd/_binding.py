@@ -1,0 +1,261 @@
+"""ctypes binding of include/grmhd.h. Argument marshalling only."""
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrmhd.so")
+
+NG = 3
+NVAR = 8
+GRMHD_OK, GRMHD_EINVAL, GRMHD_ENOMEM, GRMHD_EDEVICE, GRMHD_EUNSUPPORTED, GRMHD_ESTATE = 0, -1, -2, -3, -4, -5
+GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
+
+# every symbol include/grmhd.h declares
+EXPORTED = [
+    "grmhd_init", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
+    "grmhd_get_dt", "grmhd_step", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
+    "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
+]
+KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5}
+
+
+class GrmhdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    """Mirror of ``grmhd_problem``."""
+    _fields_ = [
+        ("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32),
+        ("coords", ctypes.c_int32),
+        ("a", ctypes.c_double), ("gam", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("x1min", ctypes.c_double), ("x1max", ctypes.c_double),
+        ("x2min", ctypes.c_double), ("x2max", ctypes.c_double),
+        ("x3min", ctypes.c_double), ("x3max", ctypes.c_double),
+        ("hslope", ctypes.c_double), ("poly_xt", ctypes.c_double),
+        ("poly_alpha", ctypes.c_double), ("mks_smooth", ctypes.c_double),
+        ("recon", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("floors", ctypes.c_int32),
+        ("rho_fl", ctypes.c_double), ("u_fl", ctypes.c_double), ("sigma_max", ctypes.c_double),
+        ("beta_min", ctypes.c_double), ("uorho_max", ctypes.c_double), ("gamma_max", ctypes.c_double),
+    ]
+
+    @classmethod
+    def from_dict(cls, prm):
+        p = cls()
+        for name, _ in cls._fields_:
+            if name == "bc":
+                for d in range(3):
+                    for s in range(2):
+                        p.bc[d][s] = int(prm["bc"][d][s])
+            else:
+                setattr(p, name, prm[name])
+        return p
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2110_10191_amd/build.py`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "grmhd_init": ([ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "grmhd_free": ([vp], ctypes.c_int),
+        "grmhd_state_layout": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
+        "grmhd_prim_to_cons": ([vp, vp, vp], ctypes.c_int),
+        "grmhd_cons_to_prim": ([vp, vp, vp, vp, i32, ctypes.POINTER(i64)], ctypes.c_int),
+        "grmhd_get_dt": ([vp, vp, dp], ctypes.c_int),
+        "grmhd_step": ([vp, vp, ctypes.c_double, dp], ctypes.c_int),
+        "grmhd_divb": ([vp, vp, dp], ctypes.c_int),
+        "grmhd_step_failures": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
+        "grmhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "grmhd_last_error": ([vp], ctypes.c_char_p),
+        "grmhd_version": ([], ctypes.c_int),
+        "grmhd_profile": ([vp, i32], ctypes.c_int),
+        "grmhd_profile_read": ([vp, i32, dp, ctypes.POINTER(i64)], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _check(status, ctx=None):
+    if status != GRMHD_OK:
+        msg = lib.grmhd_last_error(ctx).decode() or lib.grmhd_strerror(status).decode()
+        raise GrmhdError(status, msg)
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or an int address); None -> NULL."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------------- C-named calls
+
+def grmhd_init(prm, stream=None):
+    """Create a context for problem dict ``prm`` on the current device and stream."""
+    p = Problem.from_dict(prm)
+    out = ctypes.c_void_p()
+    _check(lib.grmhd_init(ctypes.byref(p), _stream_handle(stream), ctypes.byref(out)))
+    return out.value
+
+
+def grmhd_free(ctx):
+    _check(lib.grmhd_free(ctx))
+
+
+def grmhd_state_layout(ctx):
+    shape = (ctypes.c_int64 * 4)()
+    strides = (ctypes.c_int64 * 4)()
+    off = ctypes.c_int64()
+    _check(lib.grmhd_state_layout(ctx, shape, strides, ctypes.byref(off)), ctx)
+    return tuple(shape), tuple(strides), off.value
+
+
+def grmhd_prim_to_cons(ctx, P, U):
+    _check(lib.grmhd_prim_to_cons(ctx, _ptr(P), _ptr(U)), ctx)
+
+
+def grmhd_cons_to_prim(ctx, U, P, flags=None, opts=GRMHD_OPT_FLOORS | GRMHD_OPT_FIXUP, count=True):
+    nf = ctypes.c_int64(-1)
+    _check(lib.grmhd_cons_to_prim(ctx, _ptr(U), _ptr(P), _ptr(flags), opts,
+                                  ctypes.byref(nf) if count else None), ctx)
+    return nf.value if count else None
+
+
+def grmhd_get_dt(ctx, P):
+    dt = ctypes.c_double()
+    _check(lib.grmhd_get_dt(ctx, _ptr(P), ctypes.byref(dt)), ctx)
+    return dt.value
+
+
+def grmhd_step(ctx, P, dt, want_dt_next=True):
+    dn = ctypes.c_double()
+    _check(lib.grmhd_step(ctx, _ptr(P), float(dt), ctypes.byref(dn) if want_dt_next else None), ctx)
+    return dn.value if want_dt_next else None
+
+
+def grmhd_divb(ctx, P):
+    v = ctypes.c_double()
+    _check(lib.grmhd_divb(ctx, _ptr(P), ctypes.byref(v)), ctx)
+    return v.value
+
+
+def grmhd_step_failures(ctx):
+    n = ctypes.c_int64()
+    _check(lib.grmhd_step_failures(ctx, ctypes.byref(n)), ctx)
+    return n.value
+
+
+def grmhd_strerror(status):
+    return lib.grmhd_strerror(status).decode()
+
+
+def grmhd_last_error(ctx=None):
+    return lib.grmhd_last_error(ctx).decode()
+
+
+def grmhd_version():
+    return lib.grmhd_version()
+
+
+def grmhd_profile(ctx, enable):
+    _check(lib.grmhd_profile(ctx, 1 if enable else 0), ctx)
+
+
+def grmhd_profile_read(ctx, kernel):
+    """(total ms, launches) of one kernel class ('sweep1', 'update', ... or its id)."""
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(lib.grmhd_profile_read(ctx, k, ctypes.byref(ms), ctypes.byref(n)), ctx)
+    return ms.value, n.value
+
+
+# ----------------------------------------------------------------- convenience
+
+class Sim:
+    """A context plus helpers to move padded numpy states to and from the device.
+
+    Host arrays use the generator layout [8, n3+6, n2+6, n1+6]; device tensors
+    use the library layout [8, n3+6, n2+6, n1p] (x1 rows padded to 8 doubles).
+    """
+
+    def __init__(self, prm, device="cuda:0", stream=None):
+        import torch
+        self.torch = torch
+        self.prm = prm
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.ctx = grmhd_init(prm, stream)
+        self.shape, self.strides, self.offset = grmhd_state_layout(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            grmhd_free(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty_state(self):
+        return self.torch.zeros(self.shape, dtype=self.torch.float64, device=self.device)
+
+    def to_device(self, P):
+        """[8, n3+6, n2+6, n1+6] numpy -> padded device tensor."""
+        t = self.empty_state()
+        n1 = P.shape[-1]
+        t[..., :n1] = self.torch.from_numpy(P).to(self.device)
+        return t
+
+    def to_host(self, t):
+        n1 = self.prm["n1"] + 2 * NG
+        return t[..., :n1].cpu().numpy()
+
+    def interior(self, t):
+        p = self.prm
+        return t[:, NG:NG + p["n3"], NG:NG + p["n2"], NG:NG + p["n1"]]
+
+    # C-call wrappers
+    def prim_to_cons(self, P, U):
+        grmhd_prim_to_cons(self.ctx, P, U)
+
+    def cons_to_prim(self, U, P, flags=None, opts=GRMHD_OPT_FLOORS | GRMHD_OPT_FIXUP):
+        return grmhd_cons_to_prim(self.ctx, U, P, flags, opts)
+
+    def get_dt(self, P):
+        return grmhd_get_dt(self.ctx, P)
+
+    def step(self, P, dt, want_dt_next=True):
+        return grmhd_step(self.ctx, P, dt, want_dt_next)
+
+    def divb(self, P):
+        return grmhd_divb(self.ctx, P)
+
+    def step_failures(self):
+        return grmhd_step_failures(self.ctx)

@@ -1,0 +1,440 @@
+// Host side of the C ABI declared in grmhd.h: validation, context lifetime,
+// geometry set-up, and the sequencing of kernels for each call.
+//
+// One step (second-order predictor-corrector, HARM scheme):
+//   predictor: ghosts(P); sweeps(P); update(F, P_base = P, P_s = P, dt/2) -> P_h; fixup
+//   corrector: ghosts(P_h); sweeps(P_h) + ctop; update(F, P, P_h, dt) -> P; fixup
+// Everything is enqueued on the context's stream; nothing waits on the host
+// unless a host scalar is requested.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+struct ProfRecord {
+  int kernel;
+  hipEvent_t start, stop;
+};
+
+struct grmhd_ctx {
+  bool profiling = false;
+  std::vector<ProfRecord> prof;      // records since the last clear
+  std::vector<hipEvent_t> event_pool;  // events of cleared records, for reuse
+  grmhd_problem p;
+  Dims d;
+  hipStream_t stream;
+  int device;
+  bool mixed;
+  Tables t;
+  double* Ph;
+  void* F[3];
+  int8_t* flags;
+  Counters* ctr;
+  UpdateParams up;
+  double dx[3];
+  std::string err;
+};
+
+namespace {
+
+thread_local std::string g_init_error;
+
+int fail(grmhd_ctx* c, int status, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_init_error = msg;
+  return status;
+}
+
+int hip_fail(grmhd_ctx* c, hipError_t e, const char* where) {
+  std::string m = std::string(where) + ": " + hipGetErrorString(e);
+  return fail(c, GRMHD_EDEVICE, m);
+}
+
+#define HIP_OR_FAIL(ctx, call, where)            \
+  do {                                           \
+    hipError_t e_ = (call);                      \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+int validate(const grmhd_problem* p, std::string& why) {
+  if (!p) { why = "problem is NULL"; return GRMHD_EINVAL; }
+  if (p->n1 < 1 || p->n2 < 1 || p->n3 < 1) { why = "n1, n2, n3 must be >= 1"; return GRMHD_EINVAL; }
+  if (p->coords < GRMHD_MINKOWSKI_CART || p->coords > GRMHD_KERR_FMKS) { why = "unknown coords"; return GRMHD_EINVAL; }
+  if (p->recon != GRMHD_RECON_MC && p->recon != GRMHD_RECON_WENO5) { why = "unknown recon"; return GRMHD_EINVAL; }
+  if (p->precision != GRMHD_FP64 && p->precision != GRMHD_MIXED) { why = "unknown precision"; return GRMHD_EINVAL; }
+  if (!(p->gam > 1.0) || !(p->cfl > 0.0) || !std::isfinite(p->gam) || !std::isfinite(p->cfl)) {
+    why = "need gam > 1 and cfl > 0";
+    return GRMHD_EINVAL;
+  }
+  const double lo[3] = {p->x1min, p->x2min, p->x3min}, hi[3] = {p->x1max, p->x2max, p->x3max};
+  const int n[3] = {p->n1, p->n2, p->n3};
+  for (int d = 0; d < 3; ++d) {
+    if (!(hi[d] > lo[d]) || !std::isfinite(lo[d]) || !std::isfinite(hi[d])) {
+      why = "each extent needs xmax > xmin";
+      return GRMHD_EINVAL;
+    }
+    for (int s = 0; s < 2; ++s)
+      if (p->bc[d][s] < GRMHD_BC_PERIODIC || p->bc[d][s] > GRMHD_BC_DIRICHLET) {
+        why = "unknown boundary type";
+        return GRMHD_EINVAL;
+      }
+    const bool per0 = p->bc[d][0] == GRMHD_BC_PERIODIC, per1 = p->bc[d][1] == GRMHD_BC_PERIODIC;
+    if (per0 != per1) { why = "periodic boundaries must be periodic on both sides"; return GRMHD_EINVAL; }
+    if (!per0 && n[d] < NG) { why = "non-periodic directions need at least 3 zones"; return GRMHD_EINVAL; }
+    for (int s = 0; s < 2; ++s) {
+      if (p->bc[d][s] == GRMHD_BC_OUTFLOW && d != 0) { why = "outflow boundaries are x1 only"; return GRMHD_EINVAL; }
+      if (p->bc[d][s] == GRMHD_BC_POLAR && d != 1) { why = "polar boundaries are x2 only"; return GRMHD_EINVAL; }
+    }
+  }
+  if (p->coords == GRMHD_MINKOWSKI_CART) {
+    if (p->floors) { why = "floors need a Kerr metric (they depend on r)"; return GRMHD_EINVAL; }
+    if (p->bc[0][0] == GRMHD_BC_OUTFLOW || p->bc[0][1] == GRMHD_BC_OUTFLOW) {
+      why = "outflow boundaries need a Kerr metric";
+      return GRMHD_EINVAL;
+    }
+  } else {
+    if (!(std::fabs(p->a) < 1.0)) { why = "need |a| < 1"; return GRMHD_EINVAL; }
+    if (p->coords == GRMHD_KERR_FMKS && !(p->poly_xt > 0.0)) { why = "need poly_xt > 0"; return GRMHD_EINVAL; }
+  }
+  if (p->floors && !(p->sigma_max > 0 && p->uorho_max > 0 && p->gamma_max > 1.0 && p->beta_min >= 0)) {
+    why = "bad floor parameters";
+    return GRMHD_EINVAL;
+  }
+  const long long p1 = ((p->n1 + 2 * NG + 7) / 8) * 8;
+  const long long cells = p1 * (p->n2 + 2 * NG) * (long long)(p->n3 + 2 * NG);
+  if (cells * NV >= (1ll << 31)) { why = "grid too large for 32-bit indexing of one state"; return GRMHD_EINVAL; }
+  return GRMHD_OK;
+}
+
+Dims make_dims(const grmhd_problem& p) {
+  Dims d;
+  d.n1 = p.n1;
+  d.n2 = p.n2;
+  d.n3 = p.n3;
+  d.p1 = ((p.n1 + 2 * NG + 7) / 8) * 8;
+  d.p2 = p.n2 + 2 * NG;
+  d.p3 = p.n3 + 2 * NG;
+  d.s2 = d.p1;
+  d.s3 = d.p2 * d.p1;
+  d.sv = d.p3 * d.s3;
+  d.ts = d.p2 * d.p1;
+  return d;
+}
+
+void free_all(grmhd_ctx* c) {
+  void* ptrs[] = {c->t.cent, c->t.f1, c->t.f2, c->t.centf, c->t.f1f, c->t.f2f,
+                  c->Ph, c->F[0], c->F[1], c->F[2], c->flags, c->ctr};
+  for (void* q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+template <typename T>
+hipError_t dalloc(T** ptr, size_t bytes) {
+  return hipMalloc((void**)ptr, bytes);
+}
+
+hipEvent_t pooled_event(grmhd_ctx* c) {
+  if (!c->event_pool.empty()) {
+    hipEvent_t e = c->event_pool.back();
+    c->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// brackets one launch with events when profiling is on
+struct ProfScope {
+  grmhd_ctx* c;
+  ProfRecord r{};
+  bool on;
+  ProfScope(grmhd_ctx* ctx, int kernel) : c(ctx), on(ctx->profiling) {
+    if (!on) return;
+    r.kernel = kernel;
+    r.start = pooled_event(c);
+    r.stop = pooled_event(c);
+    if (!r.start || !r.stop) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(r.start, c->stream);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    (void)hipEventRecord(r.stop, c->stream);
+    c->prof.push_back(r);
+  }
+};
+
+void clear_profile(grmhd_ctx* c) {
+  for (auto& r : c->prof) {
+    c->event_pool.push_back(r.start);
+    c->event_pool.push_back(r.stop);
+  }
+  c->prof.clear();
+}
+
+// predictor or corrector substep; dsrc is the base state (source of Dirichlet ghosts)
+int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop) {
+  hipStream_t s = c->stream;
+  {
+    ProfScope ps(c, GRMHD_K_GHOSTS);
+    HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s), "ghost fill");
+  }
+  HIP_OR_FAIL(c, launch_reset(c->ctr, want_ctop ? (1 | 4) : 4, s), "reset");
+  for (int dir = 1; dir <= 3; ++dir) {
+    ProfScope ps(c, GRMHD_K_SWEEP1 + dir - 1);
+    HIP_OR_FAIL(c, launch_sweep(dir, c->p.recon, c->mixed, c->d, c->t, c->p.gam, Ps, c->F[dir - 1],
+                                want_ctop ? c->ctr->ctop : nullptr, s),
+                "sweep");
+  }
+  {
+    ProfScope ps(c, GRMHD_K_UPDATE);
+    HIP_OR_FAIL(c, launch_update(c->mixed, c->d, c->t, c->up, c->F[0], c->F[1], c->F[2], Pb, Ps, Pout,
+                                 c->flags, dt, c->ctr, s),
+                "update");
+  }
+  {
+    ProfScope ps(c, GRMHD_K_FIXUP);
+    HIP_OR_FAIL(c, launch_fixup(c->d, c->t, c->up, Pout, c->flags, c->ctr, s), "fixup");
+  }
+  return GRMHD_OK;
+}
+
+int read_dt(grmhd_ctx* c, double* dt) {
+  unsigned long long bits[3];
+  HIP_OR_FAIL(c, hipMemcpyAsync(bits, c->ctr->ctop, sizeof(bits), hipMemcpyDeviceToHost, c->stream), "copy ctop");
+  HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "synchronize");
+  double sum = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    double v;
+    std::memcpy(&v, &bits[d], sizeof(v));
+    if (!std::isfinite(v)) return fail(c, GRMHD_ESTATE, "non-finite signal speed in the state");
+    sum += v / c->dx[d];
+  }
+  *dt = sum > 0.0 ? c->p.cfl / sum : INFINITY;
+  return GRMHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int grmhd_version(void) { return 1; }
+
+const char* grmhd_strerror(int status) {
+  switch (status) {
+    case GRMHD_OK: return "ok";
+    case GRMHD_EINVAL: return "invalid argument";
+    case GRMHD_ENOMEM: return "out of device memory";
+    case GRMHD_EDEVICE: return "device or runtime error";
+    case GRMHD_EUNSUPPORTED: return "unsupported";
+    case GRMHD_ESTATE: return "non-finite state";
+    default: return "unknown status";
+  }
+}
+
+const char* grmhd_last_error(const grmhd_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_init_error.c_str();
+}
+
+int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
+  if (!out) return fail(nullptr, GRMHD_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  int st = validate(p, why);
+  if (st != GRMHD_OK) return fail(nullptr, st, why);
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, GRMHD_EDEVICE, "no HIP device");
+
+  grmhd_ctx* c = new grmhd_ctx();
+  c->p = *p;
+  c->d = make_dims(*p);
+  c->stream = (hipStream_t)hip_stream;
+  c->mixed = p->precision == GRMHD_MIXED;
+  (void)hipGetDevice(&c->device);
+  c->dx[0] = (p->x1max - p->x1min) / p->n1;
+  c->dx[1] = (p->x2max - p->x2min) / p->n2;
+  c->dx[2] = (p->x3max - p->x3min) / p->n3;
+  c->up.gam = p->gam;
+  c->up.sigma_max = p->sigma_max;
+  c->up.beta_min = p->beta_min;
+  c->up.uorho_max = p->uorho_max;
+  c->up.gamma_max = p->gamma_max;
+  c->up.dx1 = c->dx[0];
+  c->up.dx2 = c->dx[1];
+  c->up.dx3 = c->dx[2];
+  c->up.floors = p->floors ? 1 : 0;
+  c->up.polar_lo = p->bc[1][0] == GRMHD_BC_POLAR;
+  c->up.polar_hi = p->bc[1][1] == GRMHD_BC_POLAR;
+
+  const size_t ts = (size_t)c->d.ts, sv = (size_t)c->d.sv;
+  const size_t fsz = c->mixed ? sizeof(float) : sizeof(double);
+  bool ok = dalloc(&c->t.cent, N_CENT * ts * sizeof(double)) == hipSuccess &&
+            dalloc(&c->t.f1, N_FACE * ts * sizeof(double)) == hipSuccess &&
+            dalloc(&c->t.f2, N_FACE * ts * sizeof(double)) == hipSuccess &&
+            dalloc(&c->t.centf, N_FACE * ts * sizeof(float)) == hipSuccess &&
+            dalloc(&c->t.f1f, N_FACE * ts * sizeof(float)) == hipSuccess &&
+            dalloc(&c->t.f2f, N_FACE * ts * sizeof(float)) == hipSuccess &&
+            dalloc(&c->Ph, NV * sv * sizeof(double)) == hipSuccess &&
+            dalloc(&c->F[0], NV * sv * fsz) == hipSuccess && dalloc(&c->F[1], NV * sv * fsz) == hipSuccess &&
+            dalloc(&c->F[2], NV * sv * fsz) == hipSuccess && dalloc(&c->flags, sv) == hipSuccess &&
+            dalloc(&c->ctr, sizeof(Counters)) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    free_all(c);
+    delete c;
+    return fail(nullptr, GRMHD_ENOMEM, "device allocation failed");
+  }
+  // one-time clears (outside any captured work); padding stays finite
+  hipError_t e = hipMemsetAsync(c->t.cent, 0, N_CENT * ts * sizeof(double), c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->Ph, 0, NV * sv * sizeof(double), c->stream);
+  for (int q = 0; q < 3 && e == hipSuccess; ++q) e = hipMemsetAsync(c->F[q], 0, NV * sv * fsz, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->flags, 0, sv, c->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(c->ctr, 0, sizeof(Counters), c->stream);
+  if (e == hipSuccess) e = launch_geometry(c->p, c->d, c->t, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    std::string m = std::string("geometry set-up: ") + hipGetErrorString(e);
+    free_all(c);
+    delete c;
+    return fail(nullptr, GRMHD_EDEVICE, m);
+  }
+  *out = c;
+  return GRMHD_OK;
+}
+
+int grmhd_free(grmhd_ctx* ctx) {
+  if (!ctx) return GRMHD_OK;
+  (void)hipStreamSynchronize(ctx->stream);
+  clear_profile(ctx);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  free_all(ctx);
+  delete ctx;
+  return GRMHD_OK;
+}
+
+int grmhd_profile(grmhd_ctx* ctx, int32_t enable) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (enable) {
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+    clear_profile(ctx);
+  }
+  ctx->profiling = enable != 0;
+  return GRMHD_OK;
+}
+
+int grmhd_profile_read(grmhd_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!ctx || !total_ms || !launches) return GRMHD_EINVAL;
+  if (kernel < 0 || kernel >= GRMHD_K_COUNT) return fail(ctx, GRMHD_EINVAL, "profile_read: unknown kernel");
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+  double sum = 0.0;
+  int64_t n = 0;
+  for (const auto& r : ctx->prof) {
+    if (r.kernel != kernel) continue;
+    float ms = 0.0f;
+    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, r.start, r.stop), "event time");
+    sum += ms;
+    ++n;
+  }
+  *total_ms = sum;
+  *launches = n;
+  return GRMHD_OK;
+}
+
+int grmhd_state_layout(const grmhd_ctx* ctx, int64_t shape[4], int64_t strides[4], int64_t* interior_offset) {
+  if (!ctx || !shape || !strides) return GRMHD_EINVAL;
+  const Dims& d = ctx->d;
+  shape[0] = NV;
+  shape[1] = d.p3;
+  shape[2] = d.p2;
+  shape[3] = d.p1;
+  strides[0] = d.sv;
+  strides[1] = d.s3;
+  strides[2] = d.s2;
+  strides[3] = 1;
+  if (interior_offset) *interior_offset = cell_of(d, 0, 0, 0);
+  return GRMHD_OK;
+}
+
+int grmhd_prim_to_cons(grmhd_ctx* ctx, const double* P, double* U) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !U) return fail(ctx, GRMHD_EINVAL, "prim_to_cons: NULL state");
+  if (P == U) return fail(ctx, GRMHD_EINVAL, "prim_to_cons: P and U must differ");
+  HIP_OR_FAIL(ctx, launch_prim_to_cons(ctx->d, ctx->t, ctx->p.gam, P, U, ctx->stream), "prim_to_cons");
+  return GRMHD_OK;
+}
+
+int grmhd_cons_to_prim(grmhd_ctx* ctx, const double* U, double* P, int8_t* flags, int32_t opts, int64_t* n_fail) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !U) return fail(ctx, GRMHD_EINVAL, "cons_to_prim: NULL state");
+  if (P == U) return fail(ctx, GRMHD_EINVAL, "cons_to_prim: P and U must differ");
+  if (opts & ~(GRMHD_OPT_FLOORS | GRMHD_OPT_FIXUP)) return fail(ctx, GRMHD_EINVAL, "cons_to_prim: unknown opts bits");
+  UpdateParams up = ctx->up;
+  up.floors = (ctx->p.floors && (opts & GRMHD_OPT_FLOORS)) ? 1 : 0;
+  int8_t* fl = flags ? flags : ctx->flags;
+  hipStream_t s = ctx->stream;
+  HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 4, s), "reset");
+  HIP_OR_FAIL(ctx, launch_cons_to_prim(ctx->d, ctx->t, up, U, P, fl, ctx->ctr, s), "cons_to_prim");
+  if (opts & GRMHD_OPT_FIXUP) HIP_OR_FAIL(ctx, launch_fixup(ctx->d, ctx->t, up, P, fl, ctx->ctr, s), "fixup");
+  if (n_fail) {
+    unsigned int nf = 0;
+    HIP_OR_FAIL(ctx, hipMemcpyAsync(&nf, &ctx->ctr->fail, sizeof(nf), hipMemcpyDeviceToHost, s), "copy");
+    HIP_OR_FAIL(ctx, hipStreamSynchronize(s), "synchronize");
+    *n_fail = nf;
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_get_dt(grmhd_ctx* ctx, double* P, double* dt) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !dt) return fail(ctx, GRMHD_EINVAL, "get_dt: NULL argument");
+  hipStream_t s = ctx->stream;
+  HIP_OR_FAIL(ctx, launch_fill_ghosts(ctx->p, ctx->d, ctx->t, P, P, s), "ghost fill");
+  HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 1, s), "reset");
+  for (int dir = 1; dir <= 3; ++dir)
+    HIP_OR_FAIL(ctx, launch_sweep(dir, ctx->p.recon, ctx->mixed, ctx->d, ctx->t, ctx->p.gam, P, ctx->F[dir - 1],
+                                  ctx->ctr->ctop, s),
+                "sweep");
+  return read_dt(ctx, dt);
+}
+
+int grmhd_step(grmhd_ctx* ctx, double* P, double dt, double* dt_next) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P) return fail(ctx, GRMHD_EINVAL, "step: NULL state");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GRMHD_EINVAL, "step: dt must be finite and > 0");
+  HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 8, ctx->stream), "reset");
+  int st = substep(ctx, P, P, ctx->Ph, 0.5 * dt, false);
+  if (st != GRMHD_OK) return st;
+  st = substep(ctx, ctx->Ph, P, P, dt, true);
+  if (st != GRMHD_OK) return st;
+  if (dt_next) return read_dt(ctx, dt_next);
+  return GRMHD_OK;
+}
+
+int grmhd_step_failures(grmhd_ctx* ctx, int64_t* n_fail) {
+  if (!ctx || !n_fail) return GRMHD_EINVAL;
+  unsigned int nf = 0;
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&nf, &ctx->ctr->fail_total, sizeof(nf), hipMemcpyDeviceToHost, ctx->stream),
+              "copy");
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+  *n_fail = nf;
+  return GRMHD_OK;
+}
+
+int grmhd_divb(grmhd_ctx* ctx, const double* P, double* max_divb) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !max_divb) return fail(ctx, GRMHD_EINVAL, "divb: NULL argument");
+  HIP_OR_FAIL(ctx, launch_divb(ctx->p, ctx->d, ctx->t, P, ctx->ctr, ctx->stream), "divb");
+  unsigned long long bits = 0;
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&bits, &ctx->ctr->divb, sizeof(bits), hipMemcpyDeviceToHost, ctx->stream), "copy");
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+  std::memcpy(max_divb, &bits, sizeof(double));
+  return GRMHD_OK;
+}
+
+}  // extern "C"

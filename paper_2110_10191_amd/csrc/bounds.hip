@@ -1,0 +1,172 @@
+// Ghost zones, the div B monitor and counter resets.
+//
+// Ghost fill (three ghost layers), in the order x1 (interior j, k), x2 (all i,
+// interior k), x3 (all i, j) so corners are consistent:
+//   periodic  - wrap;
+//   outflow   - copy the nearest interior zone; where the copied radial
+//               four-velocity points into the domain, u~1 is reset so u^1 = 0;
+//   polar     - ghost row -1-m mirrors row m with u~2 and B2 negated;
+//   dirichlet - the ghosts keep the caller's values (copied from the base state
+//               into the half-step state).
+#include "kernels.h"
+
+namespace {
+
+__device__ inline int wrap(int x, int n) {
+  int r = x % n;
+  return r < 0 ? r + n : r;
+}
+
+// where an outflow ghost's u^1 points into the domain, set u~1 = c Gamma with
+// c = alpha g^{t1}, Gamma the positive root of
+// (1 - g11 c^2) G^2 - 2 c (g12 v2 + g13 v3) G - (1 + g_jk v^j v^k) = 0
+__device__ void inflow_fix(double* P, int stride, int c0, const double* cent, int ts, int toff,
+                           int side) {
+  Geo<double> g;
+  load_geo(g, cent, ts, toff);
+  const double v1 = P[2 * stride + c0], v2 = P[3 * stride + c0], v3 = P[4 * stride + c0];
+  const double lor = sqrt(lorentz_sq(g.gcov, v1, v2, v3));
+  const double u1 = v1 - lor * g.alpha * g.gcon[1];
+  const bool bad = side == 0 ? (u1 > 0.0) : (u1 < 0.0);
+  if (!bad) return;
+  const double c = g.alpha * g.gcon[1];
+  const double qa = 1.0 - g.gcov[4] * c * c;
+  if (!(qa > 0.0)) return;
+  const double G = g.gcov[5] * v2 + g.gcov[6] * v3;
+  const double H = g.gcov[7] * v2 * v2 + 2.0 * g.gcov[8] * v2 * v3 + g.gcov[9] * v3 * v3;
+  const double root = (c * G + sqrt(c * c * G * G + qa * (1.0 + H))) / qa;
+  P[2 * stride + c0] = c * root;
+}
+
+__global__ void ghost_x1_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
+                                double* __restrict__ P, const double* __restrict__ dsrc) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y;
+  const int k = blockIdx.z;
+  if (t >= 2 * NG) return;
+  const int side = t / NG, m = t % NG;
+  const int g = side == 0 ? -1 - m : d.n1 + m;
+  const int type = p.bc[0][side];
+  const int cg = cell_of(d, k, j, g);
+  if (type == GRMHD_BC_DIRICHLET) {
+    if (dsrc != P)
+      for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+    return;
+  }
+  const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n1) : (side == 0 ? 0 : d.n1 - 1);
+  const int cs = cell_of(d, k, j, src);
+  for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
+  if (type == GRMHD_BC_OUTFLOW) inflow_fix(P, d.sv, cg, cent, d.ts, tab_of(d, j, g), side);
+}
+
+__global__ void ghost_x2_kernel(grmhd_problem p, Dims d, double* __restrict__ P,
+                                const double* __restrict__ dsrc) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - NG;
+  const int t = blockIdx.y;
+  const int k = blockIdx.z;
+  if (i >= d.n1 + NG) return;
+  const int side = t / NG, m = t % NG;
+  const int g = side == 0 ? -1 - m : d.n2 + m;
+  const int type = p.bc[1][side];
+  const int cg = cell_of(d, k, g, i);
+  if (type == GRMHD_BC_DIRICHLET) {
+    if (dsrc != P)
+      for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+    return;
+  }
+  int src;
+  if (type == GRMHD_BC_PERIODIC) src = wrap(g, d.n2);
+  else if (type == GRMHD_BC_POLAR) src = side == 0 ? m : d.n2 - 1 - m;
+  else src = side == 0 ? 0 : d.n2 - 1;
+  const int cs = cell_of(d, k, src, i);
+  for (int v = 0; v < NV; ++v) {
+    const double q = P[v * d.sv + cs];
+    P[v * d.sv + cg] = (type == GRMHD_BC_POLAR && (v == 3 || v == 6)) ? -q : q;
+  }
+}
+
+__global__ void ghost_x3_kernel(grmhd_problem p, Dims d, double* __restrict__ P,
+                                const double* __restrict__ dsrc) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - NG;
+  const int j = (int)blockIdx.y - NG;
+  const int t = blockIdx.z;
+  if (i >= d.n1 + NG) return;
+  const int side = t / NG, m = t % NG;
+  const int g = side == 0 ? -1 - m : d.n3 + m;
+  const int type = p.bc[2][side];
+  const int cg = cell_of(d, g, j, i);
+  if (type == GRMHD_BC_DIRICHLET) {
+    if (dsrc != P)
+      for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+    return;
+  }
+  const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n3) : (side == 0 ? 0 : d.n3 - 1);
+  const int cs = cell_of(d, src, j, i);
+  for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
+}
+
+// corner-centred divergence of sqrt(-g) B; corner (i, j, k) sits at (i-1/2, j-1/2, k-1/2)
+__global__ void divb_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
+                            const double* __restrict__ P, unsigned long long* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  double val = 0.0;
+  const bool p1 = p.bc[0][0] == GRMHD_BC_PERIODIC, p2 = p.bc[1][0] == GRMHD_BC_PERIODIC,
+             p3 = p.bc[2][0] == GRMHD_BC_PERIODIC;
+  const bool ok = i < d.n1 && j < d.n2 && k < d.n3 && (p1 || i > 0) && (p2 || j > 0) && (p3 || k > 0);
+  if (ok) {
+    const int im = wrap(i - 1, d.n1), jm = wrap(j - 1, d.n2), km = wrap(k - 1, d.n3);
+    // G_d(kk, jj, ii) = sqrt(-g) B^d
+    auto G = [&](int v, int kk, int jj, int ii) {
+      return cent[T_GDET * d.ts + tab_of(d, jj, ii)] * P[(5 + v) * d.sv + cell_of(d, kk, jj, ii)];
+    };
+    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    // sum over the two transverse offsets, differencing along the direction
+    s1 = (G(0, k, j, i) - G(0, k, j, im)) + (G(0, k, jm, i) - G(0, k, jm, im)) +
+         (G(0, km, j, i) - G(0, km, j, im)) + (G(0, km, jm, i) - G(0, km, jm, im));
+    s2 = (G(1, k, j, i) - G(1, k, jm, i)) + (G(1, k, j, im) - G(1, k, jm, im)) +
+         (G(1, km, j, i) - G(1, km, jm, i)) + (G(1, km, j, im) - G(1, km, jm, im));
+    s3 = (G(2, k, j, i) - G(2, km, j, i)) + (G(2, k, j, im) - G(2, km, j, im)) +
+         (G(2, k, jm, i) - G(2, km, jm, i)) + (G(2, k, jm, im) - G(2, km, jm, im));
+    const double dx1 = (p.x1max - p.x1min) / p.n1, dx2 = (p.x2max - p.x2min) / p.n2,
+                 dx3 = (p.x3max - p.x3min) / p.n3;
+    val = fabs(s1 / (4.0 * dx1) + s2 / (4.0 * dx2) + s3 / (4.0 * dx3));
+    if (val != val) val = __builtin_inf();
+  }
+  block_max_to(val, out);
+}
+
+__global__ void reset_kernel(Counters* c, int mask) {
+  if (threadIdx.x != 0) return;
+  if (mask & 1) c->ctop[0] = c->ctop[1] = c->ctop[2] = 0ull;
+  if (mask & 2) c->divb = 0ull;
+  if (mask & 4) c->fail = 0u;
+  if (mask & 8) c->fail_total = 0u;
+}
+
+}  // namespace
+
+hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,
+                              const double* dsrc, hipStream_t s) {
+  hipLaunchKernelGGL(ghost_x1_kernel, dim3(1, d.n2, d.n3), dim3(2 * NG, 1, 1), 0, s, p, d, t.cent, P,
+                     dsrc);
+  hipLaunchKernelGGL(ghost_x2_kernel, dim3((d.n1 + 2 * NG + 63) / 64, 2 * NG, d.n3), dim3(64, 1, 1), 0,
+                     s, p, d, P, dsrc);
+  hipLaunchKernelGGL(ghost_x3_kernel, dim3((d.n1 + 2 * NG + 63) / 64, d.n2 + 2 * NG, 2 * NG),
+                     dim3(64, 1, 1), 0, s, p, d, P, dsrc);
+  return hipGetLastError();
+}
+
+hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P,
+                       Counters* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr, 2);
+  hipLaunchKernelGGL(divb_kernel, dim3((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.n3), dim3(64, 4, 1), 0, s, p,
+                     d, t.cent, P, &ctr->divb);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset(Counters* ctr, int mask, hipStream_t s) {
+  hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr, mask);
+  return hipGetLastError();
+}

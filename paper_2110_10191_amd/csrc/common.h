@@ -1,0 +1,253 @@
+// Shared device definitions of the GRMHD zone-update library (gfx950).
+//
+// Layout (see grmhd.h): a state is [8][n3+6][n2+6][n1p] float64, x1 fastest.
+// Face fluxes use the same layout: F_d at cell (k, j, i) is the flux through
+// the lower d-face of that cell. Geometry is axisymmetric and stored as 2D
+// tables [component][n2+6][n1p]: centre tables (metric, inverse, sqrt(-g),
+// lapse, connection, floor scales) and x1-/x2-face tables (metric, inverse,
+// sqrt(-g), lapse). x3 faces share the centre geometry.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "grmhd.h"
+
+#define NG GRMHD_NG
+#define NV GRMHD_NVAR
+
+// geometry table components
+enum {
+  T_GCOV = 0,     // 10: symmetric g_mn, order 00 01 02 03 11 12 13 22 23 33
+  T_GCON = 10,    // 10: g^mn, same order
+  T_GDET = 20,
+  T_ALPHA = 21,
+  N_FACE = 22,
+  T_CONN = 22,    // 40: Gamma^l_mn, l-major, (m,n) in the symmetric order
+  T_RHOFL = 62,   // rho_fl * k        (k = 1/(r^2 (1 + r/10)))
+  T_UFL = 63,     // u_fl * k^gamma
+  N_CENT = 64
+};
+
+__host__ __device__ constexpr int sidx(int m, int n) {
+  return (m <= n) ? (m * 4 - (m * (m - 1)) / 2 + (n - m)) : (n * 4 - (n * (n - 1)) / 2 + (m - n));
+}
+
+struct Dims {
+  int n1, n2, n3;
+  int p1, p2, p3;  // padded extents: n1p, n2 + 6, n3 + 6
+  int s2;          // j stride (= p1)
+  int s3;          // k stride (= p2 * p1)
+  int sv;          // variable stride (= p3 * p2 * p1)
+  int ts;          // table component stride (= p2 * p1)
+};
+
+__host__ __device__ inline int cell_of(const Dims& d, int k, int j, int i) {
+  return (k + NG) * d.s3 + (j + NG) * d.s2 + (i + NG);
+}
+__host__ __device__ inline int tab_of(const Dims& d, int j, int i) { return (j + NG) * d.s2 + (i + NG); }
+
+template <typename T>
+struct Geo {
+  T gcov[10];
+  T gcon[10];
+  T gdet;
+  T alpha;
+};
+
+template <typename T, typename S>
+__device__ inline void load_geo(Geo<T>& g, const S* __restrict__ tab, int ts, int off) {
+#pragma unroll
+  for (int c = 0; c < 10; ++c) g.gcov[c] = (T)tab[(T_GCOV + c) * ts + off];
+#pragma unroll
+  for (int c = 0; c < 10; ++c) g.gcon[c] = (T)tab[(T_GCON + c) * ts + off];
+  g.gdet = (T)tab[T_GDET * ts + off];
+  g.alpha = (T)tab[T_ALPHA * ts + off];
+}
+
+// ---------------------------------------------------------------------------
+// point physics (HARM variables; units GM = c = 1, b^2/2 magnetic pressure)
+
+template <typename T>
+struct Fluid {
+  T ucon[4], ucov[4], bcon[4], bcov[4];
+  T bsq, p, w;
+};
+
+template <typename T>
+__device__ inline T lower(const T* gcov, const T* vcon, int m) {
+  return gcov[sidx(m, 0)] * vcon[0] + gcov[sidx(m, 1)] * vcon[1] + gcov[sidx(m, 2)] * vcon[2] +
+         gcov[sidx(m, 3)] * vcon[3];
+}
+
+// Gamma^2 = 1 + g_ij u~^i u~^j
+template <typename T>
+__device__ inline T lorentz_sq(const T* gcov, T v1, T v2, T v3) {
+  return T(1) + gcov[4] * v1 * v1 + gcov[7] * v2 * v2 + gcov[9] * v3 * v3 +
+         T(2) * (gcov[5] * v1 * v2 + gcov[6] * v1 * v3 + gcov[8] * v2 * v3);
+}
+
+template <typename T>
+__device__ inline void fluid_state(const T* P, const Geo<T>& g, T gam, Fluid<T>& f) {
+  const T lor = sqrt(lorentz_sq(g.gcov, P[2], P[3], P[4]));
+  f.ucon[0] = lor / g.alpha;
+  const T la = lor * g.alpha;
+  f.ucon[1] = P[2] - la * g.gcon[1];
+  f.ucon[2] = P[3] - la * g.gcon[2];
+  f.ucon[3] = P[4] - la * g.gcon[3];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) f.ucov[m] = lower(g.gcov, f.ucon, m);
+  const T bt = P[5] * f.ucov[1] + P[6] * f.ucov[2] + P[7] * f.ucov[3];
+  const T iut = T(1) / f.ucon[0];
+  f.bcon[0] = bt;
+  f.bcon[1] = (P[5] + bt * f.ucon[1]) * iut;
+  f.bcon[2] = (P[6] + bt * f.ucon[2]) * iut;
+  f.bcon[3] = (P[7] + bt * f.ucon[3]) * iut;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) f.bcov[m] = lower(g.gcov, f.bcon, m);
+  f.bsq = f.bcon[0] * f.bcov[0] + f.bcon[1] * f.bcov[1] + f.bcon[2] * f.bcov[2] + f.bcon[3] * f.bcov[3];
+  f.p = (gam - T(1)) * P[1];
+  f.w = P[0] + P[1] + f.p;
+}
+
+// sqrt(-g) F^D for D = 1..3, or U for D = 0 (B part sqrt(-g) B exactly).
+// Energy component carries the rest-mass flux: T^D_t + rho u^D.
+template <int D, typename T>
+__device__ inline void flux_of(const T* P, const Fluid<T>& f, T gdet, T* F) {
+  const T ud = f.ucon[D];
+  const T mass = P[0] * ud;
+  const T eb = (f.w + f.bsq) * ud;
+  const T pt = f.p + T(0.5) * f.bsq;
+  const T bd = f.bcon[D];
+  F[0] = gdet * mass;
+  F[1] = gdet * (eb * f.ucov[0] - bd * f.bcov[0] + (D == 0 ? pt : T(0)) + mass);
+  F[2] = gdet * (eb * f.ucov[1] - bd * f.bcov[1] + (D == 1 ? pt : T(0)));
+  F[3] = gdet * (eb * f.ucov[2] - bd * f.bcov[2] + (D == 2 ? pt : T(0)));
+  F[4] = gdet * (eb * f.ucov[3] - bd * f.bcov[3] + (D == 3 ? pt : T(0)));
+  if (D == 0) {
+    F[5] = gdet * P[5];
+    F[6] = gdet * P[6];
+    F[7] = gdet * P[7];
+  } else {
+    F[5] = (D == 1) ? T(0) : gdet * (f.bcon[1] * ud - bd * f.ucon[1]);
+    F[6] = (D == 2) ? T(0) : gdet * (f.bcon[2] * ud - bd * f.ucon[2]);
+    F[7] = (D == 3) ? T(0) : gdet * (f.bcon[3] * ud - bd * f.ucon[3]);
+  }
+}
+
+// Fast-magnetosonic speeds dx^D/dt: roots of A l^2 + B l + C = 0 with
+// c^2 = v_A^2 + c_s^2 (1 - v_A^2).
+template <int D, typename T>
+__device__ inline void signal_speeds(const Fluid<T>& f, const Geo<T>& g, T gam, T& cmax, T& cmin) {
+  const T cs2 = gam * f.p / f.w;
+  const T va2 = f.bsq / (f.bsq + f.w);
+  const T c2 = va2 + cs2 * (T(1) - va2);
+  const T ut = f.ucon[0], ud = f.ucon[D];
+  const T A = ut * ut - c2 * (g.gcon[0] + ut * ut);
+  const T B = T(-2) * (ut * ud - c2 * (g.gcon[D] + ut * ud));
+  const T C = ud * ud - c2 * (g.gcon[sidx(D, D)] + ud * ud);
+  const T disc = sqrt(fmax(B * B - T(4) * A * C, T(0)));
+  const T i2a = T(1) / (T(2) * A);
+  const T vp = (-B + disc) * i2a;
+  const T vm = (-B - disc) * i2a;
+  cmax = fmax(vp, vm);
+  cmin = fmin(vp, vm);
+}
+
+// ---------------------------------------------------------------------------
+// reconstruction
+
+template <typename T>
+__device__ inline T mc_slope(T pm, T p0, T pp) {
+  const T dm = p0 - pm, dp = pp - p0, dc = T(0.5) * (pp - pm);
+  const T mag = fmin(fmin(T(2) * fabs(dm), T(2) * fabs(dp)), fabs(dc));
+  return (dm * dp > T(0)) ? copysign(mag, dc) : T(0);
+}
+
+// Value at the right edge of the middle zone of (x1..x5), point-value WENO5
+// with Jiang-Shu smoothness indicators and linear weights (1/16, 5/8, 5/16).
+__device__ inline double weno5_edge(double x1, double x2, double x3, double x4, double x5) {
+  const double q0 = 0.375 * x1 - 1.25 * x2 + 1.875 * x3;
+  const double q1 = -0.125 * x2 + 0.75 * x3 + 0.375 * x4;
+  const double q2 = 0.375 * x3 + 0.75 * x4 - 0.125 * x5;
+  const double t0 = x1 - 2.0 * x2 + x3, u0 = x1 - 4.0 * x2 + 3.0 * x3;
+  const double t1 = x2 - 2.0 * x3 + x4, u1 = x2 - x4;
+  const double t2 = x3 - 2.0 * x4 + x5, u2 = 3.0 * x3 - 4.0 * x4 + x5;
+  const double b0 = (13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0;
+  const double b1 = (13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1;
+  const double b2 = (13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2;
+  const double e0 = 1e-26 + b0, e1 = 1e-26 + b1, e2 = 1e-26 + b2;
+  const double a0 = 0.0625 / (e0 * e0);
+  const double a1 = 0.625 / (e1 * e1);
+  const double a2 = 0.3125 / (e2 * e2);
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+}
+
+// FP32 form: the weights as w_k = d_k / sum_j d_j ((eps+b_k)/(eps+b_j))^2, which
+// never squares eps (1e-52 is below the float range).
+__device__ inline float weno5_edge(float x1, float x2, float x3, float x4, float x5) {
+  const float q0 = 0.375f * x1 - 1.25f * x2 + 1.875f * x3;
+  const float q1 = -0.125f * x2 + 0.75f * x3 + 0.375f * x4;
+  const float q2 = 0.375f * x3 + 0.75f * x4 - 0.125f * x5;
+  const float t0 = x1 - 2.0f * x2 + x3, u0 = x1 - 4.0f * x2 + 3.0f * x3;
+  const float t1 = x2 - 2.0f * x3 + x4, u1 = x2 - x4;
+  const float t2 = x3 - 2.0f * x4 + x5, u2 = 3.0f * x3 - 4.0f * x4 + x5;
+  const float e0 = 1e-26f + ((13.0f / 12.0f) * t0 * t0 + 0.25f * u0 * u0);
+  const float e1 = 1e-26f + ((13.0f / 12.0f) * t1 * t1 + 0.25f * u1 * u1);
+  const float e2 = 1e-26f + ((13.0f / 12.0f) * t2 * t2 + 0.25f * u2 * u2);
+  const float r01 = e0 / e1, r02 = e0 / e2, r12 = e1 / e2;
+  const float w0 = 0.0625f / (0.0625f + 0.625f * r01 * r01 + 0.3125f * r02 * r02);
+  const float w1 = 0.625f / (0.0625f / (r01 * r01) + 0.625f + 0.3125f * r12 * r12);
+  const float w2 = 1.0f - w0 - w1;
+  return w0 * q0 + w1 * q1 + w2 * q2;
+}
+
+// ---------------------------------------------------------------------------
+// block reductions
+
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ inline int wave_sum(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// max of a non-negative double over the block, then one atomic max on the
+// IEEE bit pattern (order-preserving for non-negative values). Callers map NaN
+// to +inf first so a non-finite speed survives the reduction.
+__device__ inline void block_max_to(double v, unsigned long long* dst) {
+  __shared__ double part[16];
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  v = wave_max(v + 0.0);
+  if ((tid & 63) == 0) part[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    double m = part[0];
+    for (int w = 1; w < (nthr + 63) / 64; ++w) m = fmax(m, part[w]);
+    atomicMax(dst, (unsigned long long)__double_as_longlong(m + 0.0));
+  }
+}
+
+// block sum of v, then one atomic add into dst (and into dst2 when given)
+__device__ inline void block_count_to(int v, unsigned int* dst, unsigned int* dst2 = nullptr) {
+  __shared__ int cpart[16];
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  v = wave_sum(v);
+  if ((tid & 63) == 0) cpart[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    int s = 0;
+    for (int w = 0; w < (nthr + 63) / 64; ++w) s += cpart[w];
+    if (s) {
+      atomicAdd(dst, (unsigned int)s);
+      if (dst2) atomicAdd(dst2, (unsigned int)s);
+    }
+  }
+}

@@ -21,6 +21,15 @@ def gpu_available():
         return False
 
 
+def pytest_collection_modifyitems(config, items):
+    if gpu_available():
+        return
+    skip = pytest.mark.skip(reason="no GPU in this environment")
+    for item in items:
+        if "gpu" in item.keywords:
+            item.add_marker(skip)
+
+
 @pytest.fixture(scope="session")
 def lib():
     """The HIP library binding; GPU tests fail loudly when it is missing."""

@@ -1,0 +1,122 @@
+"""The C ABI boundary on the CPU: the library loads, exports every call that
+include/grmhd.h declares, the ctypes struct matches the C struct byte for byte,
+and argument validation rejects bad problems before touching a device."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import problems
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "grmhd.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(grmhd_[a-z_]+)\s*\(", text)))
+
+
+def test_header_calls_are_exported(lib):
+    declared = header_functions()
+    assert set(declared) == set(lib.EXPORTED)
+    L = ctypes.CDLL(lib.LIB_PATH)
+    for name in declared:
+        assert hasattr(L, name), name
+    for name in ("grmhd_init", "grmhd_prim_to_cons", "grmhd_step", "grmhd_cons_to_prim",
+                 "grmhd_get_dt", "grmhd_divb"):
+        assert name in declared
+
+
+def test_problem_struct_layout_matches_c(lib, tmp_path):
+    fields = [f for f, _ in lib.Problem._fields_]
+    src = tmp_path / "layout.c"
+    body = "\n".join(f'  printf("{f} %zu\\n", offsetof(grmhd_problem, {f}));' for f in fields)
+    src.write_text(f"""#include <stdio.h>
+#include <stddef.h>
+#include "grmhd.h"
+int main(void) {{
+  printf("size %zu\\n", sizeof(grmhd_problem));
+{body}
+  return 0;
+}}
+""")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line)
+    assert int(got["size"]) == ctypes.sizeof(lib.Problem)
+    for f in fields:
+        assert int(got[f]) == getattr(lib.Problem, f).offset, f
+
+
+def test_strerror_version_and_null_handling(lib):
+    assert lib.grmhd_version() >= 1
+    assert lib.grmhd_strerror(0) == "ok"
+    assert "invalid" in lib.grmhd_strerror(-1)
+    assert lib.lib.grmhd_free(None) == 0
+    assert lib.lib.grmhd_init(None, None, None) == lib.GRMHD_EINVAL
+    out = ctypes.c_void_p()
+    assert lib.lib.grmhd_init(None, None, ctypes.byref(out)) == lib.GRMHD_EINVAL
+    assert out.value is None
+    # calls on a NULL context are rejected, not dereferenced
+    assert lib.lib.grmhd_step(None, None, 0.1, None) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_get_dt(None, None, None) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_divb(None, None, None) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_prim_to_cons(None, None, None) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_cons_to_prim(None, None, None, None, 0, None) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_state_layout(None, None, None, None) == lib.GRMHD_EINVAL
+
+
+@pytest.mark.parametrize("edit,needle", [
+    (dict(n1=0), "n1"),
+    (dict(gam=1.0), "gam"),
+    (dict(cfl=0.0), "cfl"),
+    (dict(x1max=0.0), "extent"),
+    (dict(recon=7), "recon"),
+    (dict(precision=3), "precision"),
+    (dict(coords=9), "coords"),
+    (dict(bc=[[0, 1], [0, 0], [0, 0]]), "periodic"),
+    (dict(bc=[[0, 0], [1, 1], [0, 0]]), "x1 only"),
+    (dict(bc=[[2, 2], [0, 0], [0, 0]]), "x2 only"),
+    (dict(floors=1), "Kerr"),
+    (dict(n1=4000, n2=4000, n3=4000), "too large"),
+])
+def test_validation_rejects(lib, edit, needle):
+    prm, _ = problems.linear_modes(n=4)
+    prm = dict(prm)
+    prm.update(edit)
+    p = lib.Problem.from_dict(prm)
+    out = ctypes.c_void_p()
+    st = lib.lib.grmhd_init(ctypes.byref(p), None, ctypes.byref(out))
+    assert st == lib.GRMHD_EINVAL
+    assert out.value is None
+    assert needle in lib.grmhd_last_error(None)
+
+
+def test_kerr_validation(lib):
+    prm, _ = problems.fm_torus(n1=8, n2=8, n3=2)
+    prm = dict(prm)
+    prm["a"] = 1.0
+    p = lib.Problem.from_dict(prm)
+    out = ctypes.c_void_p()
+    assert lib.lib.grmhd_init(ctypes.byref(p), None, ctypes.byref(out)) == lib.GRMHD_EINVAL
+    prm["a"] = 0.5
+    prm["n2"] = 2          # polar direction with fewer than 3 zones
+    p = lib.Problem.from_dict(prm)
+    assert lib.lib.grmhd_init(ctypes.byref(p), None, ctypes.byref(out)) == lib.GRMHD_EINVAL
+
+
+def test_no_device_is_an_error_not_a_fallback(lib):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    prm, _ = problems.linear_modes(n=4)
+    p = lib.Problem.from_dict(prm)
+    out = ctypes.c_void_p()
+    assert lib.lib.grmhd_init(ctypes.byref(p), None, ctypes.byref(out)) == lib.GRMHD_EDEVICE
+    assert out.value is None

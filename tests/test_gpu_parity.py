@@ -1,0 +1,250 @@
+"""Parity of the HIP library (through its C ABI) with the CPU oracle.
+
+Bar (FP64): relative L1 per primitive <= 1e-10 after 10 steps, with both sides
+driven by the oracle's time-step sequence; pointwise calls to ~1e-13. Mixed
+precision: relative L1 <= 1e-5 against the FP64 oracle. Sizes span several
+64 x 4 thread tiles with ragged tails; the full-size torus is checked on x3
+slabs the oracle computes from a window.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import problems
+
+NG = 3
+pytestmark = pytest.mark.gpu
+
+
+def interior(P, prm):
+    return P[:, NG:NG + prm["n3"], NG:NG + prm["n2"], NG:NG + prm["n1"]]
+
+
+def rel_l1(a, b):
+    """Per-primitive sum|a - b| / sum|b| (exact zero required where sum|b| = 0)."""
+    out = []
+    for v in range(a.shape[0]):
+        num = np.abs(a[v] - b[v]).sum()
+        den = np.abs(b[v]).sum()
+        out.append(num / den if den > 0 else (0.0 if num == 0 else np.inf))
+    return np.array(out)
+
+
+def abs_terms_scale(P, g):
+    """U evaluated with |metric| and |primitives|: a per-zone upper bound of the
+    sum of the absolute values of the terms that make up each U component."""
+    prm = g.prm
+    n1, n2, n3 = g.n
+    gam = prm["gam"]
+    geo = {k: np.abs(v[..., NG:NG + n2, NG:NG + n1]) for k, v in g.cent.items()}
+    gc, gi, al = geo["gcov"], geo["gcon"], geo["alpha"]
+    A = np.abs(interior(P, prm))
+    lor = np.sqrt(1 + sum(gc[i + 1, j + 1] * A[2 + i] * A[2 + j] for i in range(3) for j in range(3)))
+    ucon = [lor / al] + [A[2 + i] + lor * al * gi[0, i + 1] for i in range(3)]
+    ucov = [sum(gc[m, n] * ucon[n] for n in range(4)) for m in range(4)]
+    bt = sum(A[5 + i] * ucov[i + 1] for i in range(3))
+    bcon = [bt] + [(A[5 + i] + bt * ucon[i + 1]) / ucon[0] for i in range(3)]
+    bcov = [sum(gc[m, n] * bcon[n] for n in range(4)) for m in range(4)]
+    bsq = sum(bcon[m] * bcov[m] for m in range(4))
+    p = (gam - 1) * A[1]
+    w = A[0] + A[1] + p
+    T = [(w + bsq) * ucon[0] * ucov[nu] + (p + 0.5 * bsq) + bcon[0] * bcov[nu] for nu in range(4)]
+    out = [A[0] * ucon[0], T[0] + A[0] * ucon[0], T[1], T[2], T[3], A[5], A[6], A[7]]
+    return np.array([geo["gdet"] * q for q in np.broadcast_arrays(*out)]) + 1e-300
+
+
+def gpu_run(lib, prm, P0, dts):
+    sim = lib.Sim(prm)
+    P = sim.to_device(P0)
+    for dt in dts:
+        sim.step(P, dt, want_dt_next=False)
+    out = sim.to_host(P)
+    sim.close()
+    return out
+
+
+def oracle_run(prm, P0, n):
+    g = oracle.Grid(prm)
+    return oracle.run(P0, g, n)
+
+
+# ----------------------------------------------------------------- pointwise calls
+
+@pytest.mark.parametrize("which", ["box", "torus"])
+def test_prim_to_cons(lib, which):
+    prm, P0 = (problems.linear_modes(n=24) if which == "box"
+               else problems.fm_torus(n1=72, n2=40, n3=6))
+    g = oracle.Grid(prm)
+    ref = oracle.prim_to_cons(P0, g)
+    sim = lib.Sim(prm)
+    P = sim.to_device(P0)
+    U = sim.empty_state()
+    sim.prim_to_cons(P, U)
+    got = interior(sim.to_host(U), prm)
+    # rounding bound: the same formula on absolute values bounds the sum of |terms|
+    # (the torus's x2 momentum is a near-cancellation, u_theta = 0 in Kerr-Schild)
+    scale = abs_terms_scale(P0, g)
+    err = np.abs(got - ref).reshape(8, -1).sum(axis=1)
+    bound = 1e-13 * scale.reshape(8, -1).sum(axis=1)
+    assert (err <= bound).all(), err / bound
+
+
+@pytest.mark.parametrize("which", ["box", "torus"])
+def test_cons_to_prim(lib, which):
+    prm, P0 = (problems.linear_modes(n=24) if which == "box"
+               else problems.fm_torus(n1=72, n2=40, n3=6))
+    g = oracle.Grid(prm)
+    U = oracle.prim_to_cons(P0, g)          # input written by the oracle
+    guess = interior(P0, prm).copy()
+    guess[0] *= 1.01
+    guess[1] *= 0.97
+    guess[2:5] *= 0.9
+    ref, failed = oracle.cons_to_prim(U, guess, g)
+    sim = lib.Sim(prm)
+    pad = ((0, 0), (NG, NG), (NG, NG), (NG, NG))
+    Ud = sim.to_device(np.pad(U, pad))
+    Pd = sim.to_device(np.pad(guess, pad))
+    nfail = sim.cons_to_prim(Ud, Pd)
+    got = interior(sim.to_host(Pd), prm)
+    assert nfail == int(failed.sum())
+    assert (rel_l1(got, ref) < 1e-13).all(), rel_l1(got, ref)
+
+
+def test_get_dt(lib):
+    for prm, P0 in (problems.linear_modes(n=32), problems.fm_torus(n1=72, n2=40, n3=6)):
+        g = oracle.Grid(prm)
+        ref = oracle.get_dt(P0, g)
+        sim = lib.Sim(prm)
+        got = sim.get_dt(sim.to_device(P0))
+        assert abs(got / ref - 1) < 1e-12, (got, ref)
+        sim.close()
+
+
+# ----------------------------------------------------------------- full steps
+
+def test_box_ten_steps_fp64(lib):
+    """3D periodic Minkowski box 32^3, slow + Alfven modes, MC, 10 steps."""
+    prm, P0 = problems.linear_modes(n=32)
+    ref, dts = oracle_run(prm, P0, 10)
+    got = gpu_run(lib, prm, P0, dts)
+    err = rel_l1(interior(got, prm), interior(ref, prm))
+    print("box rel-L1", err)
+    assert (err <= 1e-10).all(), err
+
+
+def test_torus_ten_steps_fp64(lib):
+    """Fishbone-Moncrief torus (the benchmark problem at reduced size), MC, 10 steps."""
+    prm, P0 = problems.fm_torus(n1=72, n2=40, n3=6)
+    ref, dts = oracle_run(prm, P0, 10)
+    got = gpu_run(lib, prm, P0, dts)
+    err = rel_l1(interior(got, prm), interior(ref, prm))
+    print("torus rel-L1", err)
+    assert (err <= 1e-10).all(), err
+
+
+def test_torus_weno5_fp64(lib):
+    prm, P0 = problems.fm_torus(n1=72, n2=40, n3=6, recon=problems.RECON_WENO5)
+    ref, dts = oracle_run(prm, P0, 10)
+    got = gpu_run(lib, prm, P0, dts)
+    err = rel_l1(interior(got, prm), interior(ref, prm))
+    print("torus WENO5 rel-L1", err)
+    assert (err <= 1e-10).all(), err
+
+
+def test_bondi_dirichlet_2d(lib):
+    prm, P0 = problems.bondi(n1=68, n2=36, n3=1, a=0.5)
+    ref, dts = oracle_run(prm, P0, 10)
+    got = gpu_run(lib, prm, P0, dts)
+    err = rel_l1(interior(got, prm), interior(ref, prm))
+    print("bondi rel-L1", err)
+    assert (err[:5] <= 1e-10).all(), err
+    assert (interior(got, prm)[5:] == 0.0).all()
+
+
+def test_mixed_precision_error(lib):
+    """FP32 reconstruction / fluxes / EMFs, FP64 accumulation and inversion:
+    relative L1 <= 1e-5 per primitive against the FP64 oracle after 10 steps."""
+    prm64, P0 = problems.fm_torus(n1=72, n2=40, n3=6, recon=problems.RECON_WENO5)
+    ref, dts = oracle_run(prm64, P0, 10)
+    prm = dict(prm64, precision=problems.MIXED)
+    got = gpu_run(lib, prm, P0, dts)
+    err = rel_l1(interior(got, prm), interior(ref, prm))
+    print("mixed rel-L1", err)
+    assert (err <= 1e-5).all(), err
+
+
+def test_divb_roundoff_and_parity(lib):
+    prm, P0 = problems.fm_torus(n1=72, n2=40, n3=6)
+    g = oracle.Grid(prm)
+    sim = lib.Sim(prm)
+    P = sim.to_device(P0)
+    d0 = sim.divb(P)
+    # both are round-off of O(1) terms (sqrt(-g) B ~ 1): agree to round-off
+    assert abs(d0 - oracle.divb(P0, g)) <= 1e-13
+    dt = sim.get_dt(P)
+    for _ in range(10):
+        dt = min(sim.step(P, dt), 1.3 * dt)
+    d1 = sim.divb(P)
+    assert d1 < 1e-12, d1
+    assert d0 < 1e-12, d0
+
+
+def test_dt_next_matches_oracle(lib):
+    prm, P0 = problems.fm_torus(n1=72, n2=40, n3=6)
+    g = oracle.Grid(prm)
+    dt = oracle.get_dt(P0, g)
+    _, ref, _ = oracle.step(P0, g, dt)
+    sim = lib.Sim(prm)
+    got = sim.step(sim.to_device(P0), dt)
+    assert abs(got / ref - 1) < 1e-11, (got, ref)
+
+
+def test_deterministic(lib):
+    prm, P0 = problems.fm_torus(n1=72, n2=40, n3=6)
+    a = gpu_run(lib, prm, P0, [0.05] * 3)
+    b = gpu_run(lib, prm, P0, [0.05] * 3)
+    assert np.array_equal(a, b)
+
+
+def test_failure_flags_match_oracle(lib):
+    """Host-crafted conserved states with no physical inversion are flagged on
+    both sides; the fixup then repairs them from their neighbours."""
+    prm, P0 = problems.linear_modes(n=12)
+    g = oracle.Grid(prm)
+    U = oracle.prim_to_cons(P0, g)
+    U[1, 2, 3, 4] = 50.0
+    U[2, 5, 5, 5] = 1e3
+    U[0, 7, 1, 9] = np.nan
+    guess = interior(P0, prm).copy()
+    ref, failed = oracle.cons_to_prim(U, guess, g)
+    sim = lib.Sim(prm)
+    Ud = sim.to_device(np.pad(U, ((0, 0), (NG, NG), (NG, NG), (NG, NG))))
+    Pd = sim.to_device(P0)
+    import torch
+    flags = torch.zeros(Pd.shape[1:], dtype=torch.int8, device=Pd.device)
+    n = sim.cons_to_prim(Ud, Pd, flags=flags)
+    assert n == 3 == int(failed.sum())
+    gf = flags.cpu().numpy()[NG:NG + 12, NG:NG + 12, NG:NG + 12].astype(bool)
+    assert np.array_equal(gf, failed)
+    got = interior(sim.to_host(Pd), prm)
+    assert np.isfinite(got).all()
+    assert (rel_l1(got, ref) < 1e-13).all()
+
+
+# ----------------------------------------------------------------- full size
+
+def test_full_size_torus_sampled_slabs(lib):
+    """The benchmark configuration itself (288 x 128 x 128 FMKS torus, MC, FP64),
+    in the launch configuration the benchmark times: one GPU step compared on
+    two x3 slabs (one at the periodic seam) that the oracle computes from
+    windows of the same initial state."""
+    prm, P0 = problems.fm_torus()
+    g = oracle.Grid(prm)
+    dt = 0.005          # a fixed step below this grid's Courant limit (~0.01)
+    got = interior(gpu_run(lib, prm, P0, [dt]), prm)
+    for k0 in (0, 77):
+        ref = oracle.step_window(P0, g, dt, k0, k0 + 1)
+        err = rel_l1(got[:, k0:k0 + 1], ref)
+        print("slab", k0, err)
+        assert (err <= 1e-10).all(), (k0, err)
