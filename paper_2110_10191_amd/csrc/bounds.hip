@@ -38,12 +38,15 @@ __device__ void inflow_fix(double* P, int stride, int c0, const double* cent, in
   P[2 * stride + c0] = c * root;
 }
 
-__global__ void ghost_x1_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
-                                double* __restrict__ P, const double* __restrict__ dsrc) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y;
-  const int k = blockIdx.z;
-  if (t >= 2 * NG) return;
+// one thread per (ghost column, j, k): column t in [0, 6), sides 0 and 1
+__global__ __launch_bounds__(256) void ghost_x1_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
+                                                       double* __restrict__ P, const double* __restrict__ dsrc) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * NG * d.n2 * d.n3) return;
+  const int t = idx % (2 * NG);
+  const int rest = idx / (2 * NG);
+  const int j = rest % d.n2;
+  const int k = rest / d.n2;
   const int side = t / NG, m = t % NG;
   const int g = side == 0 ? -1 - m : d.n1 + m;
   const int type = p.bc[0][side];
@@ -149,7 +152,8 @@ __global__ void reset_kernel(Counters* c, int mask) {
 
 hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,
                               const double* dsrc, hipStream_t s) {
-  hipLaunchKernelGGL(ghost_x1_kernel, dim3(1, d.n2, d.n3), dim3(2 * NG, 1, 1), 0, s, p, d, t.cent, P,
+  const int n1threads = 2 * NG * d.n2 * d.n3;
+  hipLaunchKernelGGL(ghost_x1_kernel, dim3((n1threads + 255) / 256), dim3(256, 1, 1), 0, s, p, d, t.cent, P,
                      dsrc);
   hipLaunchKernelGGL(ghost_x2_kernel, dim3((d.n1 + 2 * NG + 63) / 64, 2 * NG, d.n3), dim3(64, 1, 1), 0,
                      s, p, d, P, dsrc);

@@ -47,6 +47,41 @@ __host__ __device__ inline int cell_of(const Dims& d, int k, int j, int i) {
 }
 __host__ __device__ inline int tab_of(const Dims& d, int j, int i) { return (j + NG) * d.s2 + (i + NG); }
 
+// Loads and stores as (wave-uniform base pointer) + (32-bit unsigned byte offset):
+// the backend can then keep the base in scalar registers and share one 32-bit
+// vector offset across all components, instead of a 64-bit vector address per
+// load. Every array here is < 4 GiB per component (checked at init).
+template <typename S>
+__device__ inline S ldu(const S* base, unsigned byte_off) {
+  return *(const S*)((const char*)base + byte_off);
+}
+template <typename S>
+__device__ inline void stu(S* base, unsigned byte_off, S v) {
+  *(S*)((char*)base + byte_off) = v;
+}
+
+// Buffer-resource loads: the descriptor (base, size) sits in scalar registers,
+// the per-lane 32-bit byte offset is shared by every load of a thread, and the
+// component / neighbour offset goes into the scalar offset operand. Reads
+// beyond the descriptor's size return 0 instead of touching memory.
+constexpr int BUF_DWORD3 = 0x00020000;  // raw (untyped) buffer on CDNA
+
+struct Buf {
+  __amdgpu_buffer_rsrc_t r;
+};
+
+__device__ inline Buf make_buf(const void* base, unsigned bytes) {
+  Buf b;
+  b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, BUF_DWORD3);
+  return b;
+}
+__device__ inline double bld(const Buf& b, unsigned voff, int soff_bytes, double) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, soff_bytes, 0));
+}
+__device__ inline float bld(const Buf& b, unsigned voff, int soff_bytes, float) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, soff_bytes, 0));
+}
+
 template <typename T>
 struct Geo {
   T gcov[10];
@@ -55,14 +90,29 @@ struct Geo {
   T alpha;
 };
 
+// geometry from a table behind a buffer descriptor: component c at byte
+// offset c * ts * sizeof(S) (scalar) + point * sizeof(S) (vector)
+template <typename T, typename S>
+__device__ inline void load_geo_buf(Geo<T>& g, const Buf& tab, int ts, unsigned pt_bytes) {
+  const int cs = ts * (int)sizeof(S);
+#pragma unroll
+  for (int c = 0; c < 10; ++c) g.gcov[c] = (T)bld(tab, pt_bytes, (T_GCOV + c) * cs, S());
+#pragma unroll
+  for (int c = 0; c < 10; ++c) g.gcon[c] = (T)bld(tab, pt_bytes, (T_GCON + c) * cs, S());
+  g.gdet = (T)bld(tab, pt_bytes, T_GDET * cs, S());
+  g.alpha = (T)bld(tab, pt_bytes, T_ALPHA * cs, S());
+}
+
+// component c of a table lives at tab + c * ts; off is the 2D point index
 template <typename T, typename S>
 __device__ inline void load_geo(Geo<T>& g, const S* __restrict__ tab, int ts, int off) {
+  const unsigned bo = (unsigned)off * (unsigned)sizeof(S);
 #pragma unroll
-  for (int c = 0; c < 10; ++c) g.gcov[c] = (T)tab[(T_GCOV + c) * ts + off];
+  for (int c = 0; c < 10; ++c) g.gcov[c] = (T)ldu(tab + (size_t)(T_GCOV + c) * ts, bo);
 #pragma unroll
-  for (int c = 0; c < 10; ++c) g.gcon[c] = (T)tab[(T_GCON + c) * ts + off];
-  g.gdet = (T)tab[T_GDET * ts + off];
-  g.alpha = (T)tab[T_ALPHA * ts + off];
+  for (int c = 0; c < 10; ++c) g.gcon[c] = (T)ldu(tab + (size_t)(T_GCON + c) * ts, bo);
+  g.gdet = (T)ldu(tab + (size_t)T_GDET * ts, bo);
+  g.alpha = (T)ldu(tab + (size_t)T_ALPHA * ts, bo);
 }
 
 // ---------------------------------------------------------------------------
@@ -136,12 +186,11 @@ __device__ inline void flux_of(const T* P, const Fluid<T>& f, T gdet, T* F) {
 }
 
 // Fast-magnetosonic speeds dx^D/dt: roots of A l^2 + B l + C = 0 with
-// c^2 = v_A^2 + c_s^2 (1 - v_A^2).
+// c^2 = v_A^2 + c_s^2 (1 - v_A^2), v_A^2 = b^2/(b^2 + w), c_s^2 = gamma p / w,
+// evaluated as the equal single quotient (b^2 + gamma p)/(b^2 + w).
 template <int D, typename T>
 __device__ inline void signal_speeds(const Fluid<T>& f, const Geo<T>& g, T gam, T& cmax, T& cmin) {
-  const T cs2 = gam * f.p / f.w;
-  const T va2 = f.bsq / (f.bsq + f.w);
-  const T c2 = va2 + cs2 * (T(1) - va2);
+  const T c2 = (f.bsq + gam * f.p) / (f.bsq + f.w);
   const T ut = f.ucon[0], ud = f.ucon[D];
   const T A = ut * ut - c2 * (g.gcon[0] + ut * ut);
   const T B = T(-2) * (ut * ud - c2 * (g.gcon[D] + ut * ud));
@@ -200,6 +249,45 @@ __device__ inline float weno5_edge(float x1, float x2, float x3, float x4, float
   const float w1 = 0.625f / (0.0625f / (r01 * r01) + 0.625f + 0.3125f * r12 * r12);
   const float w2 = 1.0f - w0 - w1;
   return w0 * q0 + w1 * q1 + w2 * q2;
+}
+
+// ---------------------------------------------------------------------------
+// XCD-aware block mapping
+//
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Stencil kernels use a 1D grid of 8 * ntiles * chunk blocks, where a tile is
+// a 64 x 4 (x1, x2) patch and chunk = ceil(nk / 8): XCD x receives, in order,
+// every tile with k in [x*chunk, (x+1)*chunk). Consecutive blocks on one XCD
+// then share the tile's 2D geometry and its neighbouring x3 planes in that
+// XCD's L2 instead of refetching them once per x3 plane.
+
+constexpr int NXCD = 8;
+constexpr int TILE_X = 64;
+constexpr int TILE_Y = 4;
+
+struct TileK {
+  int i0, j0, k;
+  bool valid;
+};
+
+__device__ inline TileK xcd_tile_k(int tiles_x, int nk, int chunk) {
+  const int b = (int)blockIdx.x;
+  const int x = b % NXCD, w = b / NXCD;
+  const int tile = w / chunk;
+  TileK t;
+  t.k = x * chunk + (w - tile * chunk);
+  t.i0 = (tile % tiles_x) * TILE_X;
+  t.j0 = (tile / tiles_x) * TILE_Y;
+  t.valid = t.k < nk;
+  return t;
+}
+
+// 1D grid size for ni x nj x nk cells in 64 x 4 tiles
+inline unsigned xcd_grid(int ni, int nj, int nk, int* tiles_x, int* chunk) {
+  *tiles_x = (ni + TILE_X - 1) / TILE_X;
+  const int tiles = *tiles_x * ((nj + TILE_Y - 1) / TILE_Y);
+  *chunk = (nk + NXCD - 1) / NXCD;
+  return (unsigned)(NXCD * tiles * *chunk);
 }
 
 // ---------------------------------------------------------------------------

@@ -19,11 +19,13 @@ template <int D, int RECON, typename T>
 __global__ __launch_bounds__(256) void sweep_kernel(Dims d, const double* __restrict__ P,
                                                     const T* __restrict__ tab, T* __restrict__ F,
                                                     T gam, int lo1, int cnt1, int lo2, int cnt2,
-                                                    int lo3, unsigned long long* ctop) {
-  const int i = lo1 + (int)(blockIdx.x * 64 + threadIdx.x);
-  const int j = lo2 + (int)(blockIdx.y * 4 + threadIdx.y);
-  const int k = lo3 + (int)blockIdx.z;
-  const bool active = (i < lo1 + cnt1) && (j < lo2 + cnt2);
+                                                    int lo3, int cnt3, int tiles_x, int chunk,
+                                                    unsigned long long* ctop) {
+  const TileK t = xcd_tile_k(tiles_x, cnt3, chunk);
+  const int i = lo1 + t.i0 + (int)threadIdx.x;
+  const int j = lo2 + t.j0 + (int)threadIdx.y;
+  const int k = lo3 + t.k;
+  const bool active = t.valid && (i < lo1 + cnt1) && (j < lo2 + cnt2);
   double cmx = 0.0;
   if (active) {
     const int c = cell_of(d, k, j, i);
@@ -84,10 +86,10 @@ void launch_one(const Dims& d, const T* tab, double gam, const double* P, T* F, 
   const int lo1 = (D == 1) ? 0 : -1, c1 = (D == 1) ? d.n1 + 1 : d.n1 + 2;
   const int lo2 = (D == 2) ? 0 : -1, c2 = (D == 2) ? d.n2 + 1 : d.n2 + 2;
   const int lo3 = (D == 3) ? 0 : -1, c3 = (D == 3) ? d.n3 + 1 : d.n3 + 2;
-  dim3 blk(64, 4, 1);
-  dim3 grd((c1 + 63) / 64, (c2 + 3) / 4, c3);
-  hipLaunchKernelGGL((sweep_kernel<D, RECON, T>), grd, blk, 0, s, d, P, tab, F, (T)gam, lo1, c1, lo2, c2,
-                     lo3, ctop);
+  int tiles_x, chunk;
+  const unsigned nblk = xcd_grid(c1, c2, c3, &tiles_x, &chunk);
+  hipLaunchKernelGGL((sweep_kernel<D, RECON, T>), dim3(nblk), dim3(TILE_X, TILE_Y, 1), 0, s, d, P, tab, F,
+                     (T)gam, lo1, c1, lo2, c2, lo3, c3, tiles_x, chunk, ctop);
 }
 
 template <int RECON, typename T>

@@ -138,12 +138,13 @@ __global__ __launch_bounds__(256) void update_kernel(Dims d, const double* __res
                                                      const TF* __restrict__ F1p, const TF* __restrict__ F2p,
                                                      const TF* __restrict__ F3p, const double* Pb,
                                                      const double* __restrict__ Ps, double* Pout,
-                                                     int8_t* __restrict__ flags, double dt, Counters* ctr) {
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
+                                                     int8_t* __restrict__ flags, double dt, Counters* ctr, int tiles_x, int chunk) {
+  const TileK tk = xcd_tile_k(tiles_x, d.n3, chunk);
+  const int i = tk.i0 + threadIdx.x;
+  const int j = tk.j0 + threadIdx.y;
+  const int k = tk.k;
   int failed = 0;
-  if (i < d.n1 && j < d.n2) {
+  if (tk.valid && i < d.n1 && j < d.n2) {
     const int c = cell_of(d, k, j, i);
     const FluxView<TF> F1{F1p, d.sv}, F2{F2p, d.sv}, F3{F3p, d.sv};
     const int s1 = 1, s2 = d.s2, s3 = d.s3;
@@ -327,13 +328,15 @@ __global__ __launch_bounds__(256) void u2p_kernel(Dims d, const double* __restri
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up, const void* F1,
                          const void* F2, const void* F3, const double* Pb, const double* Ps, double* Pout,
                          int8_t* flags, double dt, Counters* ctr, hipStream_t s) {
-  dim3 blk(64, 4, 1), grd((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.n3);
+  int tiles_x, chunk;
+  const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, &tiles_x, &chunk);
+  dim3 blk(64, 4, 1), grd(nblk);
   if (mixed)
     hipLaunchKernelGGL(update_kernel<float>, grd, blk, 0, s, d, t.cent, up, (const float*)F1, (const float*)F2,
-                       (const float*)F3, Pb, Ps, Pout, flags, dt, ctr);
+                       (const float*)F3, Pb, Ps, Pout, flags, dt, ctr, tiles_x, chunk);
   else
     hipLaunchKernelGGL(update_kernel<double>, grd, blk, 0, s, d, t.cent, up, (const double*)F1,
-                       (const double*)F2, (const double*)F3, Pb, Ps, Pout, flags, dt, ctr);
+                       (const double*)F2, (const double*)F3, Pb, Ps, Pout, flags, dt, ctr, tiles_x, chunk);
   return hipGetLastError();
 }
 
