@@ -153,6 +153,35 @@ enum {
 int grmhd_profile(grmhd_ctx *ctx, int32_t enable);
 int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
+/* ---- Many independent problems advanced together.
+ *
+ * A batch groups n contexts (created with grmhd_init on the same device; all
+ * with the same recon and precision) and advances every active one with one
+ * grid per kernel phase spanning all of them, so small and uneven grids fill
+ * the device together. One step of all active jobs is captured once into a
+ * HIP graph and replayed. Each job keeps its own time step on the device:
+ * after every step dt_j <- min(cfl / sum_d(ctop_d/dx_d), 1.3 dt_j) from its own
+ * corrector signal speeds, so a job's evolution does not depend on the other
+ * jobs in the batch. Each job uses its context's scratch; a context must not
+ * be stepped on its own while it belongs to a live batch.
+ * hip_stream: the stream everything is enqueued on; NULL makes the batch
+ * create its own (graphs cannot be captured on the null stream). */
+typedef struct grmhd_batch grmhd_batch;
+int grmhd_batch_create(grmhd_ctx *const *jobs, int32_t n, void *hip_stream, grmhd_batch **out);
+/* Set the step size of every job (host array of n); asynchronous. */
+int grmhd_batch_set_dt(grmhd_batch *b, const double *dt);
+/* Read every job's current step size and status (host arrays of n, either
+ * nullable); status is 1 for a job whose signal speeds became non-finite;
+ * synchronises. */
+int grmhd_batch_get(grmhd_batch *b, double *dt, int32_t *status);
+/* nsteps steps of every job j with active[j] != 0 (active NULL: all) on state
+ * P[j] (layout of job j's context, ghosts refilled). When P or active differ
+ * from the previous call the job table is re-uploaded and the step graph
+ * re-captured (synchronises once); otherwise asynchronous. */
+int grmhd_batch_step(grmhd_batch *b, double *const *P, const int32_t *active, int32_t nsteps);
+int grmhd_batch_free(grmhd_batch *b);
+const char *grmhd_batch_last_error(const grmhd_batch *b);
+
 const char *grmhd_strerror(int status);
 const char *grmhd_last_error(const grmhd_ctx *ctx);
 int grmhd_version(void);

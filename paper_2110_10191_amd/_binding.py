@@ -16,6 +16,8 @@ EXPORTED = [
     "grmhd_init", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
     "grmhd_get_dt", "grmhd_step", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
+    "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
+    "grmhd_batch_free", "grmhd_batch_last_error",
 ]
 KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5}
 
@@ -77,6 +79,12 @@ def _load():
         "grmhd_version": ([], ctypes.c_int),
         "grmhd_profile": ([vp, i32], ctypes.c_int),
         "grmhd_profile_read": ([vp, i32, dp, ctypes.POINTER(i64)], ctypes.c_int),
+        "grmhd_batch_create": ([ctypes.POINTER(vp), i32, vp, ctypes.POINTER(vp)], ctypes.c_int),
+        "grmhd_batch_set_dt": ([vp, dp], ctypes.c_int),
+        "grmhd_batch_get": ([vp, dp, ctypes.POINTER(i32)], ctypes.c_int),
+        "grmhd_batch_step": ([vp, ctypes.POINTER(vp), ctypes.POINTER(i32), i32], ctypes.c_int),
+        "grmhd_batch_free": ([vp], ctypes.c_int),
+        "grmhd_batch_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -192,6 +200,74 @@ def grmhd_profile_read(ctx, kernel):
     n = ctypes.c_int64()
     _check(lib.grmhd_profile_read(ctx, k, ctypes.byref(ms), ctypes.byref(n)), ctx)
     return ms.value, n.value
+
+
+def _bcheck(status, b=None):
+    if status != GRMHD_OK:
+        msg = lib.grmhd_batch_last_error(b).decode() or lib.grmhd_strerror(status).decode()
+        raise GrmhdError(status, msg)
+
+
+def grmhd_batch_create(ctxs, stream=None):
+    arr = (ctypes.c_void_p * len(ctxs))(*ctxs)
+    out = ctypes.c_void_p()
+    _bcheck(lib.grmhd_batch_create(arr, len(ctxs), _stream_handle(stream), ctypes.byref(out)))
+    return out.value
+
+
+def grmhd_batch_set_dt(b, dts):
+    arr = (ctypes.c_double * len(dts))(*[float(x) for x in dts])
+    _bcheck(lib.grmhd_batch_set_dt(b, arr), b)
+
+
+def grmhd_batch_get(b, n):
+    dt = (ctypes.c_double * n)()
+    st = (ctypes.c_int32 * n)()
+    _bcheck(lib.grmhd_batch_get(b, dt, st), b)
+    return list(dt), list(st)
+
+
+def grmhd_batch_step(b, states, active=None, nsteps=1):
+    n = len(states)
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(s) if s is not None else None for s in states])
+    act = None if active is None else (ctypes.c_int32 * n)(*[1 if a else 0 for a in active])
+    _bcheck(lib.grmhd_batch_step(b, ptrs, act, int(nsteps)), b)
+
+
+def grmhd_batch_free(b):
+    _bcheck(lib.grmhd_batch_free(b))
+
+
+def grmhd_batch_last_error(b=None):
+    return lib.grmhd_batch_last_error(b).decode()
+
+
+class Batch:
+    """Several Sim objects (same recon and precision) advanced together."""
+
+    def __init__(self, sims, stream=None):
+        self.sims = list(sims)
+        self.b = grmhd_batch_create([s.ctx for s in self.sims], stream)
+
+    def set_dt(self, dts):
+        grmhd_batch_set_dt(self.b, dts)
+
+    def get(self):
+        return grmhd_batch_get(self.b, len(self.sims))
+
+    def step(self, states, active=None, nsteps=1):
+        grmhd_batch_step(self.b, states, active, nsteps)
+
+    def close(self):
+        if self.b:
+            grmhd_batch_free(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ----------------------------------------------------------------- convenience

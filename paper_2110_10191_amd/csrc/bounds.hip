@@ -1,4 +1,4 @@
-// Ghost zones, the div B monitor and counter resets.
+// Ghost zones, the div B monitor, counter resets and the per-job time step.
 //
 // Ghost fill (three ghost layers), in the order x1 (interior j, k), x2 (all i,
 // interior k), x3 (all i, j) so corners are consistent:
@@ -11,6 +11,8 @@
 #include "kernels.h"
 
 namespace {
+
+constexpr int GB = 64;  // threads per block of the x2 / x3 ghost fills
 
 __device__ inline int wrap(int x, int n) {
   int r = x % n;
@@ -38,10 +40,10 @@ __device__ void inflow_fix(double* P, int stride, int c0, const double* cent, in
   P[2 * stride + c0] = c * root;
 }
 
-// one thread per (ghost column, j, k): column t in [0, 6), sides 0 and 1
-__global__ __launch_bounds__(256) void ghost_x1_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
-                                                       double* __restrict__ P, const double* __restrict__ dsrc) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+// ---- bodies: idx / b are thread / block indices within one job's grid
+
+__device__ void ghost_x1_body(const grmhd_problem& p, const Dims& d, const double* cent, double* P,
+                              const double* dsrc, int idx) {
   if (idx >= 2 * NG * d.n2 * d.n3) return;
   const int t = idx % (2 * NG);
   const int rest = idx / (2 * NG);
@@ -62,11 +64,13 @@ __global__ __launch_bounds__(256) void ghost_x1_kernel(grmhd_problem p, Dims d, 
   if (type == GRMHD_BC_OUTFLOW) inflow_fix(P, d.sv, cg, cent, d.ts, tab_of(d, j, g), side);
 }
 
-__global__ void ghost_x2_kernel(grmhd_problem p, Dims d, double* __restrict__ P,
-                                const double* __restrict__ dsrc) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - NG;
-  const int t = blockIdx.y;
-  const int k = blockIdx.z;
+__device__ inline int ghost_tiles(const Dims& d) { return (d.n1 + 2 * NG + GB - 1) / GB; }
+
+__device__ void ghost_x2_body(const grmhd_problem& p, const Dims& d, double* P, const double* dsrc, int b) {
+  const int tiles = ghost_tiles(d);
+  const int bx = b % tiles, rest = b / tiles;
+  const int t = rest % (2 * NG), k = rest / (2 * NG);
+  const int i = bx * GB + (int)threadIdx.x - NG;
   if (i >= d.n1 + NG) return;
   const int side = t / NG, m = t % NG;
   const int g = side == 0 ? -1 - m : d.n2 + m;
@@ -88,11 +92,11 @@ __global__ void ghost_x2_kernel(grmhd_problem p, Dims d, double* __restrict__ P,
   }
 }
 
-__global__ void ghost_x3_kernel(grmhd_problem p, Dims d, double* __restrict__ P,
-                                const double* __restrict__ dsrc) {
-  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - NG;
-  const int j = (int)blockIdx.y - NG;
-  const int t = blockIdx.z;
+__device__ void ghost_x3_body(const grmhd_problem& p, const Dims& d, double* P, const double* dsrc, int b) {
+  const int tiles = ghost_tiles(d);
+  const int bx = b % tiles, rest = b / tiles;
+  const int j = rest % (d.n2 + 2 * NG) - NG, t = rest / (d.n2 + 2 * NG);
+  const int i = bx * GB + (int)threadIdx.x - NG;
   if (i >= d.n1 + NG) return;
   const int side = t / NG, m = t % NG;
   const int g = side == 0 ? -1 - m : d.n3 + m;
@@ -106,6 +110,33 @@ __global__ void ghost_x3_kernel(grmhd_problem p, Dims d, double* __restrict__ P,
   const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n3) : (side == 0 ? 0 : d.n3 - 1);
   const int cs = cell_of(d, src, j, i);
   for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
+}
+
+// ---- single-job kernels
+
+__global__ __launch_bounds__(256) void ghost_x1_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
+                                                       double* P, const double* dsrc) {
+  ghost_x1_body(p, d, cent, P, dsrc, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+}
+__global__ __launch_bounds__(GB) void ghost_x2_kernel(grmhd_problem p, Dims d, double* P, const double* dsrc) {
+  ghost_x2_body(p, d, P, dsrc, (int)blockIdx.x);
+}
+__global__ __launch_bounds__(GB) void ghost_x3_kernel(grmhd_problem p, Dims d, double* P, const double* dsrc) {
+  ghost_x3_body(p, d, P, dsrc, (int)blockIdx.x);
+}
+
+// ---- batched kernels: the block finds its job, then runs the same body
+
+template <int DIR>
+__global__ __launch_bounds__(256) void ghost_batch_kernel(BatchView bv, int corrector) {
+  const int* offs = bv.offs + (PH_GHOST1 + DIR - 1) * (bv.njobs + 1);
+  const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
+  const JobDesc& J = bv.jobs[jb];
+  const int b = (int)blockIdx.x - offs[jb];
+  double* tgt = corrector ? J.Ph : J.P;
+  if (DIR == 1) ghost_x1_body(J.p, J.d, J.t.cent, tgt, J.P, b * (int)blockDim.x + (int)threadIdx.x);
+  else if (DIR == 2) ghost_x2_body(J.p, J.d, tgt, J.P, b);
+  else ghost_x3_body(J.p, J.d, tgt, J.P, b);
 }
 
 // corner-centred divergence of sqrt(-g) B; corner (i, j, k) sits at (i-1/2, j-1/2, k-1/2)
@@ -124,14 +155,13 @@ __global__ void divb_kernel(grmhd_problem p, Dims d, const double* __restrict__ 
     auto G = [&](int v, int kk, int jj, int ii) {
       return cent[T_GDET * d.ts + tab_of(d, jj, ii)] * P[(5 + v) * d.sv + cell_of(d, kk, jj, ii)];
     };
-    double s1 = 0.0, s2 = 0.0, s3 = 0.0;
     // sum over the two transverse offsets, differencing along the direction
-    s1 = (G(0, k, j, i) - G(0, k, j, im)) + (G(0, k, jm, i) - G(0, k, jm, im)) +
-         (G(0, km, j, i) - G(0, km, j, im)) + (G(0, km, jm, i) - G(0, km, jm, im));
-    s2 = (G(1, k, j, i) - G(1, k, jm, i)) + (G(1, k, j, im) - G(1, k, jm, im)) +
-         (G(1, km, j, i) - G(1, km, jm, i)) + (G(1, km, j, im) - G(1, km, jm, im));
-    s3 = (G(2, k, j, i) - G(2, km, j, i)) + (G(2, k, j, im) - G(2, km, j, im)) +
-         (G(2, k, jm, i) - G(2, km, jm, i)) + (G(2, k, jm, im) - G(2, km, jm, im));
+    const double s1 = (G(0, k, j, i) - G(0, k, j, im)) + (G(0, k, jm, i) - G(0, k, jm, im)) +
+                      (G(0, km, j, i) - G(0, km, j, im)) + (G(0, km, jm, i) - G(0, km, jm, im));
+    const double s2 = (G(1, k, j, i) - G(1, k, jm, i)) + (G(1, k, j, im) - G(1, k, jm, im)) +
+                      (G(1, km, j, i) - G(1, km, jm, i)) + (G(1, km, j, im) - G(1, km, jm, im));
+    const double s3 = (G(2, k, j, i) - G(2, km, j, i)) + (G(2, k, j, im) - G(2, km, j, im)) +
+                      (G(2, k, jm, i) - G(2, km, jm, i)) + (G(2, k, jm, im) - G(2, km, jm, im));
     const double dx1 = (p.x1max - p.x1min) / p.n1, dx2 = (p.x2max - p.x2min) / p.n2,
                  dx3 = (p.x3max - p.x3min) / p.n3;
     val = fabs(s1 / (4.0 * dx1) + s2 / (4.0 * dx2) + s3 / (4.0 * dx3));
@@ -140,12 +170,44 @@ __global__ void divb_kernel(grmhd_problem p, Dims d, const double* __restrict__ 
   block_max_to(val, out);
 }
 
-__global__ void reset_kernel(Counters* c, int mask) {
-  if (threadIdx.x != 0) return;
+__device__ void reset_counters(Counters* c, int mask) {
   if (mask & 1) c->ctop[0] = c->ctop[1] = c->ctop[2] = 0ull;
   if (mask & 2) c->divb = 0ull;
   if (mask & 4) c->fail = 0u;
   if (mask & 8) c->fail_total = 0u;
+}
+
+__global__ void reset_kernel(Counters* c, int mask) {
+  if (threadIdx.x != 0) return;
+  reset_counters(c, mask);
+}
+
+__global__ void reset_batch_kernel(BatchView bv, int mask) {
+  const int jb = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (jb >= bv.njobs) return;
+  reset_counters(bv.jobs[jb].ctr, mask);
+}
+
+// dt <- min(cfl / sum_d (ctop_d / dx_d), 1.3 dt); a non-finite speed keeps dt
+// and raises the job's status flag
+__global__ void dt_batch_kernel(BatchView bv) {
+  const int jb = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (jb >= bv.njobs) return;
+  const JobDesc& J = bv.jobs[jb];
+  double sum = 0.0;
+  bool finite = true;
+  const double dx[3] = {J.up.dx1, J.up.dx2, J.up.dx3};
+  for (int d = 0; d < 3; ++d) {
+    const double c = __longlong_as_double((long long)J.ctr->ctop[d]);
+    finite = finite && isfinite(c);
+    sum += c / dx[d];
+  }
+  if (!finite || !(sum > 0.0)) {
+    if (!finite) *J.status = 1;
+    return;
+  }
+  const double dn = J.p.cfl / sum;
+  *J.dt = fmin(dn, 1.3 * *J.dt);
 }
 
 }  // namespace
@@ -155,10 +217,9 @@ hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Table
   const int n1threads = 2 * NG * d.n2 * d.n3;
   hipLaunchKernelGGL(ghost_x1_kernel, dim3((n1threads + 255) / 256), dim3(256, 1, 1), 0, s, p, d, t.cent, P,
                      dsrc);
-  hipLaunchKernelGGL(ghost_x2_kernel, dim3((d.n1 + 2 * NG + 63) / 64, 2 * NG, d.n3), dim3(64, 1, 1), 0,
-                     s, p, d, P, dsrc);
-  hipLaunchKernelGGL(ghost_x3_kernel, dim3((d.n1 + 2 * NG + 63) / 64, d.n2 + 2 * NG, 2 * NG),
-                     dim3(64, 1, 1), 0, s, p, d, P, dsrc);
+  const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
+  hipLaunchKernelGGL(ghost_x2_kernel, dim3(tiles * 2 * NG * d.n3), dim3(GB, 1, 1), 0, s, p, d, P, dsrc);
+  hipLaunchKernelGGL(ghost_x3_kernel, dim3(tiles * (d.n2 + 2 * NG) * 2 * NG), dim3(GB, 1, 1), 0, s, p, d, P, dsrc);
   return hipGetLastError();
 }
 
@@ -173,4 +234,33 @@ hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, c
 hipError_t launch_reset(Counters* ctr, int mask, hipStream_t s) {
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr, mask);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s) {
+  hipLaunchKernelGGL(ghost_batch_kernel<1>, dim3(totals[PH_GHOST1]), dim3(256), 0, s, bv, corrector ? 1 : 0);
+  hipLaunchKernelGGL(ghost_batch_kernel<2>, dim3(totals[PH_GHOST2]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
+  hipLaunchKernelGGL(ghost_batch_kernel<3>, dim3(totals[PH_GHOST3]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_reset(const BatchView& bv, int mask, hipStream_t s) {
+  hipLaunchKernelGGL(reset_batch_kernel, dim3((bv.njobs + 63) / 64), dim3(64), 0, s, bv, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_dt(const BatchView& bv, hipStream_t s) {
+  hipLaunchKernelGGL(dt_batch_kernel, dim3((bv.njobs + 63) / 64), dim3(64), 0, s, bv);
+  return hipGetLastError();
+}
+
+void job_phase_blocks(const Dims& d, int counts[PH_COUNT]) {
+  counts[PH_GHOST1] = (2 * NG * d.n2 * d.n3 + 255) / 256;
+  const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
+  counts[PH_GHOST2] = tiles * 2 * NG * d.n3;
+  counts[PH_GHOST3] = tiles * (d.n2 + 2 * NG) * 2 * NG;
+  int tx, ch;
+  counts[PH_SWEEP1] = (int)xcd_grid(d.n1 + 1, d.n2 + 2, d.n3 + 2, &tx, &ch);
+  counts[PH_SWEEP2] = (int)xcd_grid(d.n1 + 2, d.n2 + 1, d.n3 + 2, &tx, &ch);
+  counts[PH_SWEEP3] = (int)xcd_grid(d.n1 + 2, d.n2 + 2, d.n3 + 1, &tx, &ch);
+  counts[PH_UPDATE] = (int)xcd_grid(d.n1, d.n2, d.n3, &tx, &ch);
 }

@@ -270,8 +270,9 @@ struct TileK {
   bool valid;
 };
 
-__device__ inline TileK xcd_tile_k(int tiles_x, int nk, int chunk) {
-  const int b = (int)blockIdx.x;
+// b: block index within this job's grid (a multiple-of-8 offset from the
+// launch's block index, so b % 8 is still the XCD)
+__device__ inline TileK xcd_tile_k(int b, int tiles_x, int nk, int chunk) {
   const int x = b % NXCD, w = b / NXCD;
   const int tile = w / chunk;
   TileK t;

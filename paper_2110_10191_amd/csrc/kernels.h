@@ -32,6 +32,57 @@ struct UpdateParams {
   int polar_lo, polar_hi;  // x2 boundaries are polar axes
 };
 
+// ---------------------------------------------------------------------------
+// batched launches: one grid per phase spans every job of a batch
+
+// one job of a batch (lives in device memory)
+struct JobDesc {
+  grmhd_problem p;
+  Dims d;
+  Tables t;
+  UpdateParams up;
+  double* P;        // the job's state (caller-owned)
+  double* Ph;       // half-step state
+  void* F[3];       // face fluxes (double or float)
+  int8_t* flags;
+  Counters* ctr;
+  double* dt;       // device scalar: the job's step size for the next step
+  int* status;      // device scalar: set to 1 when a non-finite speed appears
+};
+
+enum { PH_GHOST1 = 0, PH_GHOST2, PH_GHOST3, PH_SWEEP1, PH_SWEEP2, PH_SWEEP3, PH_UPDATE, PH_COUNT };
+
+// offs[ph * (njobs + 1) + j] = first block of job j in phase ph; entry njobs = total
+struct BatchView {
+  const JobDesc* jobs;
+  const int* offs;
+  int njobs;
+};
+
+__device__ inline int batch_job(const int* offs, int njobs, int b) {
+  int lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (offs[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// per-phase block counts of one job (stencil phases are multiples of 8)
+void job_phase_blocks(const Dims& d, int counts[PH_COUNT]);
+
+// corrector = false: predictor (ghosts of P, fluxes of P, P_base = P -> P_h, dt/2);
+// corrector = true: ghosts of P_h, fluxes of P_h, (P, P_h) -> P with dt.
+// totals[ph] = grid size of phase ph over the batch.
+hipError_t launch_batch_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s);
+hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon, bool mixed, bool corrector,
+                               bool want_ctop, hipStream_t s);
+hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, hipStream_t s);
+hipError_t launch_batch_reset(const BatchView& bv, int mask, hipStream_t s);
+// dt <- min(cfl / sum_d(ctop_d / dx_d), 1.3 dt) per job, on the device
+hipError_t launch_batch_dt(const BatchView& bv, hipStream_t s);
+
 hipError_t launch_geometry(const grmhd_problem& p, const Dims& d, const Tables& t, hipStream_t s);
 
 hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,

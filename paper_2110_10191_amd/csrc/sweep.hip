@@ -15,17 +15,24 @@
 
 namespace {
 
+template <int D>
+struct FaceRange {
+  int lo1, c1, lo2, c2, lo3, c3;
+  __host__ __device__ explicit FaceRange(const Dims& d)
+      : lo1(D == 1 ? 0 : -1), c1(D == 1 ? d.n1 + 1 : d.n1 + 2), lo2(D == 2 ? 0 : -1),
+        c2(D == 2 ? d.n2 + 1 : d.n2 + 2), lo3(D == 3 ? 0 : -1), c3(D == 3 ? d.n3 + 1 : d.n3 + 2) {}
+};
+
+// b: block index within this job's grid
 template <int D, int RECON, typename T>
-__global__ __launch_bounds__(256) void sweep_kernel(Dims d, const double* __restrict__ P,
-                                                    const T* __restrict__ tab, T* __restrict__ F,
-                                                    T gam, int lo1, int cnt1, int lo2, int cnt2,
-                                                    int lo3, int cnt3, int tiles_x, int chunk,
-                                                    unsigned long long* ctop) {
-  const TileK t = xcd_tile_k(tiles_x, cnt3, chunk);
-  const int i = lo1 + t.i0 + (int)threadIdx.x;
-  const int j = lo2 + t.j0 + (int)threadIdx.y;
-  const int k = lo3 + t.k;
-  const bool active = t.valid && (i < lo1 + cnt1) && (j < lo2 + cnt2);
+__device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T* __restrict__ tab,
+                           T* __restrict__ F, T gam, int b, unsigned long long* ctop) {
+  const FaceRange<D> fr(d);
+  const TileK t = xcd_tile_k(b, (fr.c1 + TILE_X - 1) / TILE_X, fr.c3, (fr.c3 + NXCD - 1) / NXCD);
+  const int i = fr.lo1 + t.i0 + (int)threadIdx.x;
+  const int j = fr.lo2 + t.j0 + (int)threadIdx.y;
+  const int k = fr.lo3 + t.k;
+  const bool active = t.valid && (i < fr.lo1 + fr.c1) && (j < fr.lo2 + fr.c2);
   double cmx = 0.0;
   if (active) {
     const int c = cell_of(d, k, j, i);
@@ -35,9 +42,9 @@ __global__ __launch_bounds__(256) void sweep_kernel(Dims d, const double* __rest
     for (int v = 0; v < NV; ++v) {
       const double* q = P + v * d.sv + c;
       if (RECON == GRMHD_RECON_MC) {
-        const T a = (T)q[-2 * st], b = (T)q[-st], e = (T)q[0], f = (T)q[st];
-        PL[v] = b + T(0.5) * mc_slope(a, b, e);
-        PR[v] = e - T(0.5) * mc_slope(b, e, f);
+        const T a = (T)q[-2 * st], bb = (T)q[-st], e = (T)q[0], f = (T)q[st];
+        PL[v] = bb + T(0.5) * mc_slope(a, bb, e);
+        PR[v] = e - T(0.5) * mc_slope(bb, e, f);
       } else {
         const T x0 = (T)q[-3 * st], x1 = (T)q[-2 * st], x2 = (T)q[-st], x3 = (T)q[0],
                 x4 = (T)q[st], x5 = (T)q[2 * st];
@@ -81,15 +88,40 @@ __global__ __launch_bounds__(256) void sweep_kernel(Dims d, const double* __rest
 }
 
 template <int D, int RECON, typename T>
+__global__ __launch_bounds__(256) void sweep_kernel(Dims d, const double* __restrict__ P, const T* __restrict__ tab,
+                                                    T* __restrict__ F, T gam, unsigned long long* ctop) {
+  sweep_body<D, RECON, T>(d, P, tab, F, gam, (int)blockIdx.x, ctop);
+}
+
+template <typename T>
+__device__ inline const T* face_table(const Tables& t, int dir);
+template <>
+__device__ inline const double* face_table<double>(const Tables& t, int dir) {
+  return dir == 1 ? t.f1 : (dir == 2 ? t.f2 : t.cent);
+}
+template <>
+__device__ inline const float* face_table<float>(const Tables& t, int dir) {
+  return dir == 1 ? t.f1f : (dir == 2 ? t.f2f : t.centf);
+}
+
+// every job of a batch in one grid; predictor sweeps P, corrector sweeps P_h
+template <int D, int RECON, typename T>
+__global__ __launch_bounds__(256) void sweep_batch_kernel(BatchView bv, int corrector, int want_ctop) {
+  const int* offs = bv.offs + (PH_SWEEP1 + D - 1) * (bv.njobs + 1);
+  const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
+  const JobDesc& J = bv.jobs[jb];
+  sweep_body<D, RECON, T>(J.d, corrector ? J.Ph : J.P, face_table<T>(J.t, D), (T*)J.F[D - 1], (T)J.p.gam,
+                          (int)blockIdx.x - offs[jb], want_ctop ? J.ctr->ctop : nullptr);
+}
+
+template <int D, int RECON, typename T>
 void launch_one(const Dims& d, const T* tab, double gam, const double* P, T* F, unsigned long long* ctop,
                 hipStream_t s) {
-  const int lo1 = (D == 1) ? 0 : -1, c1 = (D == 1) ? d.n1 + 1 : d.n1 + 2;
-  const int lo2 = (D == 2) ? 0 : -1, c2 = (D == 2) ? d.n2 + 1 : d.n2 + 2;
-  const int lo3 = (D == 3) ? 0 : -1, c3 = (D == 3) ? d.n3 + 1 : d.n3 + 2;
+  const FaceRange<D> fr(d);
   int tiles_x, chunk;
-  const unsigned nblk = xcd_grid(c1, c2, c3, &tiles_x, &chunk);
+  const unsigned nblk = xcd_grid(fr.c1, fr.c2, fr.c3, &tiles_x, &chunk);
   hipLaunchKernelGGL((sweep_kernel<D, RECON, T>), dim3(nblk), dim3(TILE_X, TILE_Y, 1), 0, s, d, P, tab, F,
-                     (T)gam, lo1, c1, lo2, c2, lo3, c3, tiles_x, chunk, ctop);
+                     (T)gam, ctop);
 }
 
 template <int RECON, typename T>
@@ -98,6 +130,15 @@ void launch_dir(int dir, const Dims& d, const T* cent, const T* f1, const T* f2,
   if (dir == 1) launch_one<1, RECON, T>(d, f1, gam, P, F, ctop, s);
   else if (dir == 2) launch_one<2, RECON, T>(d, f2, gam, P, F, ctop, s);
   else launch_one<3, RECON, T>(d, cent, gam, P, F, ctop, s);
+}
+
+template <int RECON, typename T>
+void launch_batch_dirs(const BatchView& bv, const int* totals, bool corrector, bool want_ctop, hipStream_t s) {
+  const dim3 blk(TILE_X, TILE_Y, 1);
+  const int c = corrector ? 1 : 0, w = want_ctop ? 1 : 0;
+  hipLaunchKernelGGL((sweep_batch_kernel<1, RECON, T>), dim3(totals[PH_SWEEP1]), blk, 0, s, bv, c, w);
+  hipLaunchKernelGGL((sweep_batch_kernel<2, RECON, T>), dim3(totals[PH_SWEEP2]), blk, 0, s, bv, c, w);
+  hipLaunchKernelGGL((sweep_batch_kernel<3, RECON, T>), dim3(totals[PH_SWEEP3]), blk, 0, s, bv, c, w);
 }
 
 }  // namespace
@@ -114,6 +155,18 @@ hipError_t launch_sweep(int dir, int recon, bool mixed, const Dims& d, const Tab
       launch_dir<GRMHD_RECON_MC, double>(dir, d, t.cent, t.f1, t.f2, gam, P, (double*)F, ctop, s);
     else
       launch_dir<GRMHD_RECON_WENO5, double>(dir, d, t.cent, t.f1, t.f2, gam, P, (double*)F, ctop, s);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon, bool mixed, bool corrector,
+                               bool want_ctop, hipStream_t s) {
+  if (mixed) {
+    if (recon == GRMHD_RECON_MC) launch_batch_dirs<GRMHD_RECON_MC, float>(bv, totals, corrector, want_ctop, s);
+    else launch_batch_dirs<GRMHD_RECON_WENO5, float>(bv, totals, corrector, want_ctop, s);
+  } else {
+    if (recon == GRMHD_RECON_MC) launch_batch_dirs<GRMHD_RECON_MC, double>(bv, totals, corrector, want_ctop, s);
+    else launch_batch_dirs<GRMHD_RECON_WENO5, double>(bv, totals, corrector, want_ctop, s);
   }
   return hipGetLastError();
 }

@@ -133,13 +133,13 @@ struct FluxView {
   __device__ TF raw(int v, int c) const { return F[v * sv + c]; }
 };
 
+// b: block index within this job's grid (64 x 4 tiles, XCD-aware order)
 template <typename TF>
-__global__ __launch_bounds__(256) void update_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
-                                                     const TF* __restrict__ F1p, const TF* __restrict__ F2p,
-                                                     const TF* __restrict__ F3p, const double* Pb,
-                                                     const double* __restrict__ Ps, double* Pout,
-                                                     int8_t* __restrict__ flags, double dt, Counters* ctr, int tiles_x, int chunk) {
-  const TileK tk = xcd_tile_k(tiles_x, d.n3, chunk);
+__device__ void update_body(const Dims& d, const double* __restrict__ cent, const UpdateParams& up,
+                            const TF* __restrict__ F1p, const TF* __restrict__ F2p, const TF* __restrict__ F3p,
+                            const double* Pb, const double* __restrict__ Ps, double* Pout,
+                            int8_t* __restrict__ flags, double dt, Counters* ctr, int b) {
+  const TileK tk = xcd_tile_k(b, (d.n1 + TILE_X - 1) / TILE_X, d.n3, (d.n3 + NXCD - 1) / NXCD);
   const int i = tk.i0 + threadIdx.x;
   const int j = tk.j0 + threadIdx.y;
   const int k = tk.k;
@@ -243,16 +243,36 @@ __global__ __launch_bounds__(256) void update_kernel(Dims d, const double* __res
   block_count_to(failed, &ctr->fail, &ctr->fail_total);
 }
 
+template <typename TF>
+__global__ __launch_bounds__(256) void update_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
+                                                     const TF* __restrict__ F1, const TF* __restrict__ F2,
+                                                     const TF* __restrict__ F3, const double* Pb,
+                                                     const double* __restrict__ Ps, double* Pout,
+                                                     int8_t* __restrict__ flags, double dt, Counters* ctr) {
+  update_body<TF>(d, cent, up, F1, F2, F3, Pb, Ps, Pout, flags, dt, ctr, (int)blockIdx.x);
+}
+
+// every job of a batch: predictor P -> P_h with dt/2, corrector (P, P_h) -> P with dt
+template <typename TF>
+__global__ __launch_bounds__(256) void update_batch_kernel(BatchView bv, int corrector) {
+  const int* offs = bv.offs + PH_UPDATE * (bv.njobs + 1);
+  const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
+  const JobDesc& J = bv.jobs[jb];
+  const double dt = corrector ? *J.dt : 0.5 * *J.dt;
+  update_body<TF>(J.d, J.t.cent, J.up, (const TF*)J.F[0], (const TF*)J.F[1], (const TF*)J.F[2], J.P,
+                  corrector ? J.Ph : J.P, corrector ? J.P : J.Ph, J.flags, dt, J.ctr, (int)blockIdx.x - offs[jb]);
+}
+
 // failed zone <- mean of the hydro primitives of its non-failed interior
 // neighbours among the 26 (values before any repair), then the bounds
-__global__ __launch_bounds__(256) void fixup_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
-                                                    double* P, const int8_t* __restrict__ flags,
-                                                    const Counters* ctr) {
+__device__ void fixup_body(const Dims& d, const double* __restrict__ cent, const UpdateParams& up, double* P,
+                           const int8_t* __restrict__ flags, const Counters* ctr, int b) {
   if (ctr->fail == 0u) return;
-  const int i = blockIdx.x * 64 + threadIdx.x;
-  const int j = blockIdx.y * 4 + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= d.n1 || j >= d.n2) return;
+  const TileK tk = xcd_tile_k(b, (d.n1 + TILE_X - 1) / TILE_X, d.n3, (d.n3 + NXCD - 1) / NXCD);
+  const int i = tk.i0 + (int)threadIdx.x;
+  const int j = tk.j0 + (int)threadIdx.y;
+  const int k = tk.k;
+  if (!tk.valid || i >= d.n1 || j >= d.n2) return;
   const int c = cell_of(d, k, j, i);
   if (!flags[c]) return;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
@@ -279,6 +299,19 @@ __global__ __launch_bounds__(256) void fixup_kernel(Dims d, const double* __rest
     apply_floors(pn, g, cent[T_RHOFL * d.ts + toff], cent[T_UFL * d.ts + toff], up);
   }
   for (int v = 0; v < 5; ++v) P[v * d.sv + c] = pn[v];
+}
+
+__global__ __launch_bounds__(256) void fixup_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
+                                                    double* P, const int8_t* __restrict__ flags,
+                                                    const Counters* ctr) {
+  fixup_body(d, cent, up, P, flags, ctr, (int)blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void fixup_batch_kernel(BatchView bv, int corrector) {
+  const int* offs = bv.offs + PH_UPDATE * (bv.njobs + 1);
+  const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
+  const JobDesc& J = bv.jobs[jb];
+  fixup_body(J.d, J.t.cent, J.up, corrector ? J.P : J.Ph, J.flags, J.ctr, (int)blockIdx.x - offs[jb]);
 }
 
 __global__ __launch_bounds__(256) void p2u_kernel(Dims d, const double* __restrict__ cent, double gam,
@@ -330,20 +363,30 @@ hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const Updat
                          int8_t* flags, double dt, Counters* ctr, hipStream_t s) {
   int tiles_x, chunk;
   const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, &tiles_x, &chunk);
-  dim3 blk(64, 4, 1), grd(nblk);
+  dim3 blk(TILE_X, TILE_Y, 1), grd(nblk);
   if (mixed)
     hipLaunchKernelGGL(update_kernel<float>, grd, blk, 0, s, d, t.cent, up, (const float*)F1, (const float*)F2,
-                       (const float*)F3, Pb, Ps, Pout, flags, dt, ctr, tiles_x, chunk);
+                       (const float*)F3, Pb, Ps, Pout, flags, dt, ctr);
   else
     hipLaunchKernelGGL(update_kernel<double>, grd, blk, 0, s, d, t.cent, up, (const double*)F1,
-                       (const double*)F2, (const double*)F3, Pb, Ps, Pout, flags, dt, ctr, tiles_x, chunk);
+                       (const double*)F2, (const double*)F3, Pb, Ps, Pout, flags, dt, ctr);
   return hipGetLastError();
 }
 
 hipError_t launch_fixup(const Dims& d, const Tables& t, const UpdateParams& up, double* P, const int8_t* flags,
                         const Counters* ctr, hipStream_t s) {
-  dim3 blk(64, 4, 1), grd((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.n3);
-  hipLaunchKernelGGL(fixup_kernel, grd, blk, 0, s, d, t.cent, up, P, flags, ctr);
+  int tiles_x, chunk;
+  const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, &tiles_x, &chunk);
+  hipLaunchKernelGGL(fixup_kernel, dim3(nblk), dim3(TILE_X, TILE_Y, 1), 0, s, d, t.cent, up, P, flags, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, hipStream_t s) {
+  const dim3 blk(TILE_X, TILE_Y, 1), grd(totals[PH_UPDATE]);
+  const int c = corrector ? 1 : 0;
+  if (mixed) hipLaunchKernelGGL(update_batch_kernel<float>, grd, blk, 0, s, bv, c);
+  else hipLaunchKernelGGL(update_batch_kernel<double>, grd, blk, 0, s, bv, c);
+  hipLaunchKernelGGL(fixup_batch_kernel, grd, blk, 0, s, bv, c);
   return hipGetLastError();
 }
 
