@@ -64,6 +64,9 @@ enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2, GRMHD_BC_DIRICHLET = 3 };
 enum { GRMHD_OPT_FLOORS = 1, GRMHD_OPT_FIXUP = 2 };
 
+/* Only the calls below are exported from the shared library. */
+#define GRMHD_API __attribute__((visibility("default")))
+
 #define GRMHD_NG 3
 #define GRMHD_NVAR 8
 
@@ -98,19 +101,19 @@ typedef struct grmhd_ctx grmhd_ctx;
  * inverse, sqrt(-g), lapse at zone centres and faces; connection at centres by
  * centred differences) and allocate scratch. hip_stream: a hipStream_t, or NULL
  * for the null stream. Errors: EINVAL (bad problem), ENOMEM, EDEVICE. */
-int grmhd_init(const grmhd_problem *p, void *hip_stream, grmhd_ctx **out);
+GRMHD_API int grmhd_init(const grmhd_problem *p, void *hip_stream, grmhd_ctx **out);
 
 /* Release everything the context owns. NULL is accepted. */
-int grmhd_free(grmhd_ctx *ctx);
+GRMHD_API int grmhd_free(grmhd_ctx *ctx);
 
 /* shape = {8, n3+6, n2+6, n1p}, strides in elements, and the element offset
  * of interior zone (0,0,0) of variable 0. */
-int grmhd_state_layout(const grmhd_ctx *ctx, int64_t shape[4], int64_t strides[4],
+GRMHD_API int grmhd_state_layout(const grmhd_ctx *ctx, int64_t shape[4], int64_t strides[4],
                        int64_t *interior_offset);
 
 /* Conserved variables of the interior zones of P (ghosts of U are not
  * written). Functionality / Implementation Notes: U(P) is the analytic map. */
-int grmhd_prim_to_cons(grmhd_ctx *ctx, const double *P, double *U);
+GRMHD_API int grmhd_prim_to_cons(grmhd_ctx *ctx, const double *P, double *U);
 
 /* 1D_W inversion of the interior zones (Implementation Notes). P is the
  * Newton guess on entry and the result on exit. opts: GRMHD_OPT_FLOORS applies
@@ -118,28 +121,28 @@ int grmhd_prim_to_cons(grmhd_ctx *ctx, const double *P, double *U);
  * from their neighbours. flags (nullable, same zone layout as one variable of
  * a state, int8): 1 where the inversion failed, 0 elsewhere (interior only).
  * n_fail (nullable, host): number of failed zones; synchronises. */
-int grmhd_cons_to_prim(grmhd_ctx *ctx, const double *U, double *P, int8_t *flags,
+GRMHD_API int grmhd_cons_to_prim(grmhd_ctx *ctx, const double *U, double *P, int8_t *flags,
                        int32_t opts, int64_t *n_fail);
 
 /* Courant step of state P: dt = cfl / sum_d (max_faces ctop_d / dx_d) with
  * ctop the LLF signal speed at each face. Refills the ghost zones of P.
  * dt (host) is written; synchronises. */
-int grmhd_get_dt(grmhd_ctx *ctx, double *P, double *dt);
+GRMHD_API int grmhd_get_dt(grmhd_ctx *ctx, double *P, double *dt);
 
 /* One second-order predictor-corrector step of size dt, in place on P
  * (ghosts refilled). dt_next (nullable, host): the Courant step from the
  * corrector's signal speeds; synchronises when given. Returns GRMHD_ESTATE if
  * a non-finite signal speed appeared (only checked when dt_next is given). */
-int grmhd_step(grmhd_ctx *ctx, double *P, double dt, double *dt_next);
+GRMHD_API int grmhd_step(grmhd_ctx *ctx, double *P, double dt, double *dt_next);
 
 /* max |div B| over cell corners, with div B the corner-centred divergence of
  * sqrt(-g) B (the quantity Flux-CT keeps at round-off, Implementation Notes).
  * Corners on non-periodic boundaries are excluded. Reads interior zones only.
  * max_divb (host) is written; synchronises. */
-int grmhd_divb(grmhd_ctx *ctx, const double *P, double *max_divb);
+GRMHD_API int grmhd_divb(grmhd_ctx *ctx, const double *P, double *max_divb);
 
 /* Failed-inversion count of the last grmhd_step (both substeps); synchronises. */
-int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
+GRMHD_API int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
 
 /* Kernel timing for measurement. grmhd_profile(ctx, 1) clears the record and
  * starts bracketing every kernel launch of grmhd_step with HIP events on the
@@ -150,8 +153,17 @@ enum {
   GRMHD_K_GHOSTS = 0, GRMHD_K_SWEEP1 = 1, GRMHD_K_SWEEP2 = 2, GRMHD_K_SWEEP3 = 3,
   GRMHD_K_UPDATE = 4, GRMHD_K_FIXUP = 5, GRMHD_K_COUNT = 6
 };
-int grmhd_profile(grmhd_ctx *ctx, int32_t enable);
-int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+GRMHD_API int grmhd_profile(grmhd_ctx *ctx, int32_t enable);
+GRMHD_API int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Thread-block tile of the sweep kernels (GRMHD_TILE_SWEEP) or of the update
+ * and fixup kernels (GRMHD_TILE_UPDATE): tx zones along x1 by ty along x2, one
+ * thread per zone; tx a power of two in [16, 256], tx * ty a multiple of 64 and
+ * at most 256. Default 64 x 4. Results do not depend on the tile. A batch uses
+ * the tiles of its first job for every job. */
+enum { GRMHD_TILE_SWEEP = 0, GRMHD_TILE_UPDATE = 1 };
+GRMHD_API int grmhd_set_tiles(grmhd_ctx *ctx, int32_t which, int32_t tx, int32_t ty);
+GRMHD_API int grmhd_get_tiles(const grmhd_ctx *ctx, int32_t which, int32_t *tx, int32_t *ty);
 
 /* ---- Many independent problems advanced together.
  *
@@ -167,24 +179,24 @@ int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t
  * hip_stream: the stream everything is enqueued on; NULL makes the batch
  * create its own (graphs cannot be captured on the null stream). */
 typedef struct grmhd_batch grmhd_batch;
-int grmhd_batch_create(grmhd_ctx *const *jobs, int32_t n, void *hip_stream, grmhd_batch **out);
+GRMHD_API int grmhd_batch_create(grmhd_ctx *const *jobs, int32_t n, void *hip_stream, grmhd_batch **out);
 /* Set the step size of every job (host array of n); asynchronous. */
-int grmhd_batch_set_dt(grmhd_batch *b, const double *dt);
+GRMHD_API int grmhd_batch_set_dt(grmhd_batch *b, const double *dt);
 /* Read every job's current step size and status (host arrays of n, either
  * nullable); status is 1 for a job whose signal speeds became non-finite;
  * synchronises. */
-int grmhd_batch_get(grmhd_batch *b, double *dt, int32_t *status);
+GRMHD_API int grmhd_batch_get(grmhd_batch *b, double *dt, int32_t *status);
 /* nsteps steps of every job j with active[j] != 0 (active NULL: all) on state
  * P[j] (layout of job j's context, ghosts refilled). When P or active differ
  * from the previous call the job table is re-uploaded and the step graph
  * re-captured (synchronises once); otherwise asynchronous. */
-int grmhd_batch_step(grmhd_batch *b, double *const *P, const int32_t *active, int32_t nsteps);
-int grmhd_batch_free(grmhd_batch *b);
-const char *grmhd_batch_last_error(const grmhd_batch *b);
+GRMHD_API int grmhd_batch_step(grmhd_batch *b, double *const *P, const int32_t *active, int32_t nsteps);
+GRMHD_API int grmhd_batch_free(grmhd_batch *b);
+GRMHD_API const char *grmhd_batch_last_error(const grmhd_batch *b);
 
-const char *grmhd_strerror(int status);
-const char *grmhd_last_error(const grmhd_ctx *ctx);
-int grmhd_version(void);
+GRMHD_API const char *grmhd_strerror(int status);
+GRMHD_API const char *grmhd_last_error(const grmhd_ctx *ctx);
+GRMHD_API int grmhd_version(void);
 
 #ifdef __cplusplus
 }

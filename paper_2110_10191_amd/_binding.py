@@ -16,10 +16,11 @@ EXPORTED = [
     "grmhd_init", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
     "grmhd_get_dt", "grmhd_step", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
-    "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
+    "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
     "grmhd_batch_free", "grmhd_batch_last_error",
 ]
 KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5}
+TILES = {"sweep": 0, "update": 1}
 
 
 class GrmhdError(RuntimeError):
@@ -62,6 +63,11 @@ class Problem(ctypes.Structure):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_2110_10191_amd/build.py`")
+    # torch's HIP runtime must be the one in the process: torch asks the loader
+    # for "libamdhip64.so" and the library for "libamdhip64.so.7", so loading
+    # the library first would bring in a second runtime that torch then does
+    # not share. Imported first, torch's copy satisfies both names.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     sig = {
@@ -79,6 +85,8 @@ def _load():
         "grmhd_version": ([], ctypes.c_int),
         "grmhd_profile": ([vp, i32], ctypes.c_int),
         "grmhd_profile_read": ([vp, i32, dp, ctypes.POINTER(i64)], ctypes.c_int),
+        "grmhd_set_tiles": ([vp, i32, i32, i32], ctypes.c_int),
+        "grmhd_get_tiles": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
         "grmhd_batch_create": ([ctypes.POINTER(vp), i32, vp, ctypes.POINTER(vp)], ctypes.c_int),
         "grmhd_batch_set_dt": ([vp, dp], ctypes.c_int),
         "grmhd_batch_get": ([vp, dp, ctypes.POINTER(i32)], ctypes.c_int),
@@ -200,6 +208,20 @@ def grmhd_profile_read(ctx, kernel):
     n = ctypes.c_int64()
     _check(lib.grmhd_profile_read(ctx, k, ctypes.byref(ms), ctypes.byref(n)), ctx)
     return ms.value, n.value
+
+
+def grmhd_set_tiles(ctx, which, tx, ty):
+    """Block tile (tx along x1, ty along x2) of the 'sweep' or 'update' kernels."""
+    w = TILES[which] if isinstance(which, str) else int(which)
+    _check(lib.grmhd_set_tiles(ctx, w, int(tx), int(ty)), ctx)
+
+
+def grmhd_get_tiles(ctx, which):
+    w = TILES[which] if isinstance(which, str) else int(which)
+    tx = ctypes.c_int32()
+    ty = ctypes.c_int32()
+    _check(lib.grmhd_get_tiles(ctx, w, ctypes.byref(tx), ctypes.byref(ty)), ctx)
+    return tx.value, ty.value
 
 
 def _bcheck(status, b=None):
@@ -335,3 +357,9 @@ class Sim:
 
     def step_failures(self):
         return grmhd_step_failures(self.ctx)
+
+    def set_tiles(self, which, tx, ty):
+        grmhd_set_tiles(self.ctx, which, tx, ty)
+
+    def get_tiles(self, which):
+        return grmhd_get_tiles(self.ctx, which)

@@ -22,7 +22,7 @@ BUILD_DIR = os.path.join(HERE, "_build")
 
 ARCH = os.environ.get("GRMHD_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
     "-I", INCLUDE, "-I", CSRC,

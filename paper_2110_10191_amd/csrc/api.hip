@@ -97,6 +97,8 @@ Dims make_dims(const grmhd_problem& p) {
   d.s3 = d.p2 * d.p1;
   d.sv = d.p3 * d.s3;
   d.ts = d.p2 * d.p1;
+  d.stx = d.utx = TILE_X;
+  d.sty = d.uty = TILE_Y;
   return d;
 }
 
@@ -225,7 +227,10 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
   int st = validate(p, why);
   if (st != GRMHD_OK) return fail(nullptr, st, why);
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(nullptr, GRMHD_EDEVICE, "no HIP device");
+  const hipError_t de = hipGetDeviceCount(&ndev);
+  if (de != hipSuccess || ndev < 1)
+    return fail(nullptr, GRMHD_EDEVICE,
+                std::string("no HIP device (hipGetDeviceCount: ") + hipGetErrorString(de) + ")");
 
   grmhd_ctx* c = new grmhd_ctx();
   c->p = *p;
@@ -291,6 +296,37 @@ int grmhd_free(grmhd_ctx* ctx) {
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   free_all(ctx);
   delete ctx;
+  return GRMHD_OK;
+}
+
+int grmhd_set_tiles(grmhd_ctx* ctx, int32_t which, int32_t tx, int32_t ty) {
+  if (!ctx) return GRMHD_EINVAL;
+  const bool pow2 = tx >= 16 && tx <= 256 && (tx & (tx - 1)) == 0;
+  if (!pow2 || ty < 1 || tx * ty > 256 || (tx * ty) % 64 != 0)
+    return fail(ctx, GRMHD_EINVAL, "set_tiles: need tx a power of two in [16, 256], tx*ty a multiple of 64, <= 256");
+  if (which == GRMHD_TILE_SWEEP) {
+    ctx->d.stx = tx;
+    ctx->d.sty = ty;
+  } else if (which == GRMHD_TILE_UPDATE) {
+    ctx->d.utx = tx;
+    ctx->d.uty = ty;
+  } else {
+    return fail(ctx, GRMHD_EINVAL, "set_tiles: unknown kernel class");
+  }
+  return GRMHD_OK;
+}
+
+int grmhd_get_tiles(const grmhd_ctx* ctx, int32_t which, int32_t* tx, int32_t* ty) {
+  if (!ctx || !tx || !ty) return GRMHD_EINVAL;
+  if (which == GRMHD_TILE_SWEEP) {
+    *tx = ctx->d.stx;
+    *ty = ctx->d.sty;
+  } else if (which == GRMHD_TILE_UPDATE) {
+    *tx = ctx->d.utx;
+    *ty = ctx->d.uty;
+  } else {
+    return GRMHD_EINVAL;
+  }
   return GRMHD_OK;
 }
 

@@ -30,6 +30,7 @@ struct grmhd_batch {
   std::vector<int32_t> cur_active;
   int totals[PH_COUNT] = {0};
   int nactive = 0;
+  int stx = TILE_X, sty = TILE_Y, utx = TILE_X, uty = TILE_Y;  // tiles of every job
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::string err;
@@ -60,7 +61,7 @@ void drop_graph(grmhd_batch* b) {
 
 // enqueue one step of every job in the current job table
 hipError_t enqueue_step(grmhd_batch* b) {
-  const BatchView bv{b->d_jobs, b->d_offs, b->nactive};
+  const BatchView bv{b->d_jobs, b->d_offs, b->nactive, b->stx, b->sty, b->utx, b->uty};
   hipError_t e;
   if ((e = launch_batch_reset(bv, 8, b->stream)) != hipSuccess) return e;
   for (int corr = 0; corr < 2; ++corr) {
@@ -85,6 +86,10 @@ int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
     std::memset(&jd, 0, sizeof(jd));
     jd.p = c->p;
     jd.d = c->d;
+    jd.d.stx = b->stx;
+    jd.d.sty = b->sty;
+    jd.d.utx = b->utx;
+    jd.d.uty = b->uty;
     jd.t = c->t;
     jd.up = c->up;
     jd.P = P[j];
@@ -98,7 +103,7 @@ int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
     jd.status = b->d_status + j;
     jobs.push_back(jd);
     int cnt[PH_COUNT];
-    job_phase_blocks(c->d, cnt);
+    job_phase_blocks(jd.d, cnt);
     counts.insert(counts.end(), cnt, cnt + PH_COUNT);
   }
   const int na = (int)jobs.size();
@@ -165,6 +170,10 @@ int grmhd_batch_create(grmhd_ctx* const* jobs, int32_t n, void* hip_stream, grmh
   b->ctx.assign(jobs, jobs + n);
   b->recon = jobs[0]->p.recon;
   b->mixed = jobs[0]->mixed;
+  b->stx = jobs[0]->d.stx;
+  b->sty = jobs[0]->d.sty;
+  b->utx = jobs[0]->d.utx;
+  b->uty = jobs[0]->d.uty;
   b->stream = (hipStream_t)hip_stream;
   hipError_t e = hipSuccess;
   if (!b->stream) {

@@ -40,6 +40,8 @@ struct Dims {
   int s3;          // k stride (= p2 * p1)
   int sv;          // variable stride (= p3 * p2 * p1)
   int ts;          // table component stride (= p2 * p1)
+  int stx, sty;    // thread-block tile (x1 x x2) of the sweeps
+  int utx, uty;    // thread-block tile of the update and fixup
 };
 
 __host__ __device__ inline int cell_of(const Dims& d, int k, int j, int i) {
@@ -256,13 +258,14 @@ __device__ inline float weno5_edge(float x1, float x2, float x3, float x4, float
 //
 // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
 // Stencil kernels use a 1D grid of 8 * ntiles * chunk blocks, where a tile is
-// a 64 x 4 (x1, x2) patch and chunk = ceil(nk / 8): XCD x receives, in order,
-// every tile with k in [x*chunk, (x+1)*chunk). Consecutive blocks on one XCD
-// then share the tile's 2D geometry and its neighbouring x3 planes in that
-// XCD's L2 instead of refetching them once per x3 plane.
+// a tx x ty (x1, x2) patch (one thread per cell, the block's shape) and
+// chunk = ceil(nk / 8): XCD x receives, in order, every tile with k in
+// [x*chunk, (x+1)*chunk). Consecutive blocks on one XCD then share the tile's
+// 2D geometry and its neighbouring x3 planes in that XCD's L2 instead of
+// refetching them once per x3 plane.
 
 constexpr int NXCD = 8;
-constexpr int TILE_X = 64;
+constexpr int TILE_X = 64;   // default tile
 constexpr int TILE_Y = 4;
 
 struct TileK {
@@ -272,23 +275,24 @@ struct TileK {
 
 // b: block index within this job's grid (a multiple-of-8 offset from the
 // launch's block index, so b % 8 is still the XCD)
-__device__ inline TileK xcd_tile_k(int b, int tiles_x, int nk, int chunk) {
+__device__ inline TileK xcd_tile_k(int b, int tx, int ty, int ni, int nk) {
+  const int tiles_x = (ni + tx - 1) / tx;
+  const int chunk = (nk + NXCD - 1) / NXCD;
   const int x = b % NXCD, w = b / NXCD;
   const int tile = w / chunk;
   TileK t;
   t.k = x * chunk + (w - tile * chunk);
-  t.i0 = (tile % tiles_x) * TILE_X;
-  t.j0 = (tile / tiles_x) * TILE_Y;
+  t.i0 = (tile % tiles_x) * tx;
+  t.j0 = (tile / tiles_x) * ty;
   t.valid = t.k < nk;
   return t;
 }
 
-// 1D grid size for ni x nj x nk cells in 64 x 4 tiles
-inline unsigned xcd_grid(int ni, int nj, int nk, int* tiles_x, int* chunk) {
-  *tiles_x = (ni + TILE_X - 1) / TILE_X;
-  const int tiles = *tiles_x * ((nj + TILE_Y - 1) / TILE_Y);
-  *chunk = (nk + NXCD - 1) / NXCD;
-  return (unsigned)(NXCD * tiles * *chunk);
+// 1D grid size for ni x nj x nk cells in tx x ty tiles
+inline unsigned xcd_grid(int ni, int nj, int nk, int tx, int ty) {
+  const int tiles = ((ni + tx - 1) / tx) * ((nj + ty - 1) / ty);
+  const int chunk = (nk + NXCD - 1) / NXCD;
+  return (unsigned)(NXCD * tiles * chunk);
 }
 
 // ---------------------------------------------------------------------------

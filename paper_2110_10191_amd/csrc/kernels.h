@@ -57,6 +57,7 @@ struct BatchView {
   const JobDesc* jobs;
   const int* offs;
   int njobs;
+  int stx, sty, utx, uty;  // block tiles shared by every job of the batch
 };
 
 __device__ inline int batch_job(const int* offs, int njobs, int b) {

@@ -28,7 +28,7 @@ template <int D, int RECON, typename T>
 __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T* __restrict__ tab,
                            T* __restrict__ F, T gam, int b, unsigned long long* ctop) {
   const FaceRange<D> fr(d);
-  const TileK t = xcd_tile_k(b, (fr.c1 + TILE_X - 1) / TILE_X, fr.c3, (fr.c3 + NXCD - 1) / NXCD);
+  const TileK t = xcd_tile_k(b, d.stx, d.sty, fr.c1, fr.c3);
   const int i = fr.lo1 + t.i0 + (int)threadIdx.x;
   const int j = fr.lo2 + t.j0 + (int)threadIdx.y;
   const int k = fr.lo3 + t.k;
@@ -118,9 +118,8 @@ template <int D, int RECON, typename T>
 void launch_one(const Dims& d, const T* tab, double gam, const double* P, T* F, unsigned long long* ctop,
                 hipStream_t s) {
   const FaceRange<D> fr(d);
-  int tiles_x, chunk;
-  const unsigned nblk = xcd_grid(fr.c1, fr.c2, fr.c3, &tiles_x, &chunk);
-  hipLaunchKernelGGL((sweep_kernel<D, RECON, T>), dim3(nblk), dim3(TILE_X, TILE_Y, 1), 0, s, d, P, tab, F,
+  const unsigned nblk = xcd_grid(fr.c1, fr.c2, fr.c3, d.stx, d.sty);
+  hipLaunchKernelGGL((sweep_kernel<D, RECON, T>), dim3(nblk), dim3(d.stx, d.sty, 1), 0, s, d, P, tab, F,
                      (T)gam, ctop);
 }
 
@@ -134,7 +133,7 @@ void launch_dir(int dir, const Dims& d, const T* cent, const T* f1, const T* f2,
 
 template <int RECON, typename T>
 void launch_batch_dirs(const BatchView& bv, const int* totals, bool corrector, bool want_ctop, hipStream_t s) {
-  const dim3 blk(TILE_X, TILE_Y, 1);
+  const dim3 blk(bv.stx, bv.sty, 1);
   const int c = corrector ? 1 : 0, w = want_ctop ? 1 : 0;
   hipLaunchKernelGGL((sweep_batch_kernel<1, RECON, T>), dim3(totals[PH_SWEEP1]), blk, 0, s, bv, c, w);
   hipLaunchKernelGGL((sweep_batch_kernel<2, RECON, T>), dim3(totals[PH_SWEEP2]), blk, 0, s, bv, c, w);

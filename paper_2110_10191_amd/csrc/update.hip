@@ -139,7 +139,7 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
                             const TF* __restrict__ F1p, const TF* __restrict__ F2p, const TF* __restrict__ F3p,
                             const double* Pb, const double* __restrict__ Ps, double* Pout,
                             int8_t* __restrict__ flags, double dt, Counters* ctr, int b) {
-  const TileK tk = xcd_tile_k(b, (d.n1 + TILE_X - 1) / TILE_X, d.n3, (d.n3 + NXCD - 1) / NXCD);
+  const TileK tk = xcd_tile_k(b, d.utx, d.uty, d.n1, d.n3);
   const int i = tk.i0 + threadIdx.x;
   const int j = tk.j0 + threadIdx.y;
   const int k = tk.k;
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void update_batch_kernel(BatchView bv, int cor
 __device__ void fixup_body(const Dims& d, const double* __restrict__ cent, const UpdateParams& up, double* P,
                            const int8_t* __restrict__ flags, const Counters* ctr, int b) {
   if (ctr->fail == 0u) return;
-  const TileK tk = xcd_tile_k(b, (d.n1 + TILE_X - 1) / TILE_X, d.n3, (d.n3 + NXCD - 1) / NXCD);
+  const TileK tk = xcd_tile_k(b, d.utx, d.uty, d.n1, d.n3);
   const int i = tk.i0 + (int)threadIdx.x;
   const int j = tk.j0 + (int)threadIdx.y;
   const int k = tk.k;
@@ -361,9 +361,8 @@ __global__ __launch_bounds__(256) void u2p_kernel(Dims d, const double* __restri
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up, const void* F1,
                          const void* F2, const void* F3, const double* Pb, const double* Ps, double* Pout,
                          int8_t* flags, double dt, Counters* ctr, hipStream_t s) {
-  int tiles_x, chunk;
-  const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, &tiles_x, &chunk);
-  dim3 blk(TILE_X, TILE_Y, 1), grd(nblk);
+  const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
+  dim3 blk(d.utx, d.uty, 1), grd(nblk);
   if (mixed)
     hipLaunchKernelGGL(update_kernel<float>, grd, blk, 0, s, d, t.cent, up, (const float*)F1, (const float*)F2,
                        (const float*)F3, Pb, Ps, Pout, flags, dt, ctr);
@@ -375,14 +374,13 @@ hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const Updat
 
 hipError_t launch_fixup(const Dims& d, const Tables& t, const UpdateParams& up, double* P, const int8_t* flags,
                         const Counters* ctr, hipStream_t s) {
-  int tiles_x, chunk;
-  const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, &tiles_x, &chunk);
-  hipLaunchKernelGGL(fixup_kernel, dim3(nblk), dim3(TILE_X, TILE_Y, 1), 0, s, d, t.cent, up, P, flags, ctr);
+  const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
+  hipLaunchKernelGGL(fixup_kernel, dim3(nblk), dim3(d.utx, d.uty, 1), 0, s, d, t.cent, up, P, flags, ctr);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, hipStream_t s) {
-  const dim3 blk(TILE_X, TILE_Y, 1), grd(totals[PH_UPDATE]);
+  const dim3 blk(bv.utx, bv.uty, 1), grd(totals[PH_UPDATE]);
   const int c = corrector ? 1 : 0;
   if (mixed) hipLaunchKernelGGL(update_batch_kernel<float>, grd, blk, 0, s, bv, c);
   else hipLaunchKernelGGL(update_batch_kernel<double>, grd, blk, 0, s, bv, c);

@@ -5,6 +5,7 @@ and argument validation rejects bad problems before touching a device."""
 import ctypes
 import os
 import re
+import shutil
 import subprocess
 
 import pytest
@@ -120,3 +121,25 @@ def test_no_device_is_an_error_not_a_fallback(lib):
     out = ctypes.c_void_p()
     assert lib.lib.grmhd_init(ctypes.byref(p), None, ctypes.byref(out)) == lib.GRMHD_EDEVICE
     assert out.value is None
+
+
+def test_library_exports_exactly_the_header_calls(lib):
+    nm = shutil.which("nm")
+    if nm is None:
+        pytest.skip("nm is not available")
+    out = subprocess.run([nm, "-D", "--defined-only", lib.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    names = {ln.split()[-1] for ln in out.splitlines() if ln.strip()}
+    # header-instantiated library templates and HIP's per-unit ids aside, the
+    # library's own internals (launchers, context type) stay hidden
+    assert {n for n in names if n.startswith("grmhd_")} == set(header_functions())
+    assert not [n for n in names if "launch_" in n or "grmhd_ctx" in n or "Dims" in n]
+
+
+def test_null_context_calls_are_rejected(lib):
+    i32 = ctypes.c_int32
+    tx, ty = i32(), i32()
+    assert lib.lib.grmhd_set_tiles(None, 0, 64, 4) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_get_tiles(None, 0, ctypes.byref(tx), ctypes.byref(ty)) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_profile(None, 1) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_step(None, None, 0.1, None) == lib.GRMHD_EINVAL
