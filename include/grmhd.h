@@ -103,6 +103,12 @@ typedef struct grmhd_ctx grmhd_ctx;
  * for the null stream. Errors: EINVAL (bad problem), ENOMEM, EDEVICE. */
 GRMHD_API int grmhd_init(const grmhd_problem *p, void *hip_stream, grmhd_ctx **out);
 
+/* Device memory a context for problem p would own (geometry tables and
+ * scratch: ctx_bytes) and the size of one caller-owned state (state_bytes),
+ * without touching a device; for admission under a memory budget.
+ * Errors: EINVAL (bad problem or NULL argument). */
+GRMHD_API int grmhd_context_bytes(const grmhd_problem *p, int64_t *ctx_bytes, int64_t *state_bytes);
+
 /* Release everything the context owns. NULL is accepted. */
 GRMHD_API int grmhd_free(grmhd_ctx *ctx);
 

@@ -13,7 +13,7 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 
 # every symbol include/grmhd.h declares
 EXPORTED = [
-    "grmhd_init", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
+    "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
     "grmhd_get_dt", "grmhd_step", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
@@ -73,6 +73,7 @@ def _load():
     sig = {
         "grmhd_init": ([ctypes.POINTER(Problem), vp, ctypes.POINTER(vp)], ctypes.c_int),
         "grmhd_free": ([vp], ctypes.c_int),
+        "grmhd_context_bytes": ([ctypes.POINTER(Problem), ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_state_layout": ([vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_prim_to_cons": ([vp, vp, vp], ctypes.c_int),
         "grmhd_cons_to_prim": ([vp, vp, vp, vp, i32, ctypes.POINTER(i64)], ctypes.c_int),
@@ -136,6 +137,15 @@ def grmhd_init(prm, stream=None):
     out = ctypes.c_void_p()
     _check(lib.grmhd_init(ctypes.byref(p), _stream_handle(stream), ctypes.byref(out)))
     return out.value
+
+
+def grmhd_context_bytes(prm):
+    """(context bytes, one state's bytes) a problem needs on the device."""
+    p = Problem.from_dict(prm)
+    cb = ctypes.c_int64()
+    sb = ctypes.c_int64()
+    _check(lib.grmhd_context_bytes(ctypes.byref(p), ctypes.byref(cb), ctypes.byref(sb)))
+    return cb.value, sb.value
 
 
 def grmhd_free(ctx):

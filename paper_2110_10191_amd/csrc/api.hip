@@ -220,6 +220,21 @@ const char* grmhd_last_error(const grmhd_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_init_error.c_str();
 }
 
+int grmhd_context_bytes(const grmhd_problem* p, int64_t* ctx_bytes, int64_t* state_bytes) {
+  if (!p || !ctx_bytes || !state_bytes) return fail(nullptr, GRMHD_EINVAL, "context_bytes: NULL argument");
+  std::string why;
+  const int st = validate(p, why);
+  if (st != GRMHD_OK) return fail(nullptr, st, why);
+  const Dims d = make_dims(*p);
+  const size_t ts = (size_t)d.ts, sv = (size_t)d.sv;
+  const size_t fsz = p->precision == GRMHD_MIXED ? sizeof(float) : sizeof(double);
+  const size_t tables = (N_CENT + 2 * N_FACE) * ts * sizeof(double) + 3 * N_FACE * ts * sizeof(float);
+  const size_t scratch = NV * sv * sizeof(double) + 3 * NV * sv * fsz + sv + sizeof(Counters);
+  *ctx_bytes = (int64_t)(tables + scratch);
+  *state_bytes = (int64_t)(NV * sv * sizeof(double));
+  return GRMHD_OK;
+}
+
 int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
   if (!out) return fail(nullptr, GRMHD_EINVAL, "out is NULL");
   *out = nullptr;
@@ -255,6 +270,7 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
 
   const size_t ts = (size_t)c->d.ts, sv = (size_t)c->d.sv;
   const size_t fsz = c->mixed ? sizeof(float) : sizeof(double);
+  // keep in step with context_bytes()
   bool ok = dalloc(&c->t.cent, N_CENT * ts * sizeof(double)) == hipSuccess &&
             dalloc(&c->t.f1, N_FACE * ts * sizeof(double)) == hipSuccess &&
             dalloc(&c->t.f2, N_FACE * ts * sizeof(double)) == hipSuccess &&

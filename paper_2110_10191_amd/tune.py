@@ -193,6 +193,54 @@ def tune_sim(sim, P, steps=3, repeats=3, default=(64, 4)):
     return result, timings
 
 
+def search(measure, default=(64, 4), repeats=3):
+    """Coordinate search over the two tile classes with a caller's timer.
+
+    measure(tiles) -> seconds (or ms) of some fixed work run with
+    tiles = {"sweep": (tx, ty), "update": (tx, ty)}. The sweep tile is chosen
+    with the update tile at the default, then the update tile with the chosen
+    sweep tile. Returns (tiles, {cls: best median})."""
+    tiles = {"sweep": default, "update": default}
+    best_t = {}
+    for cls in ("sweep", "update"):
+        times = {}
+        for tile in _ordered(default):
+            trial = dict(tiles, **{cls: tile})
+            times[tile] = [measure(trial) for _ in range(repeats)]
+        tiles[cls], best_t[cls] = pick(times)
+    return tiles, best_t
+
+
+def tune_batch(sims, states, steps=3, repeats=3, stream=None):
+    """Tiles for a batch of Sim objects (the batch takes its first job's tiles),
+    timed on whole batched steps; the states advance. Leaves the best tiles set
+    on sims[0] and returns them with their per-step times in ms."""
+    import time
+    import torch
+
+    dts = [s.get_dt(P) for s, P in zip(sims, states)]
+
+    def measure(tiles):
+        sims[0].set_tiles("sweep", *tiles["sweep"])
+        sims[0].set_tiles("update", *tiles["update"])
+        b = B.Batch(sims, stream=stream)
+        try:
+            b.set_dt(dts)
+            b.step(states, nsteps=1)             # capture + warm
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.step(states, nsteps=steps)
+            b.get()                              # synchronises the batch stream
+            return (time.perf_counter() - t0) / steps * 1e3
+        finally:
+            b.close()
+
+    tiles, best = search(measure, repeats=repeats)
+    sims[0].set_tiles("sweep", *tiles["sweep"])
+    sims[0].set_tiles("update", *tiles["update"])
+    return tiles, best
+
+
 def tune_problem(prm, P0, cache=None, force=False, steps=3, repeats=3, device="cuda:0"):
     """Tiles for problem ``prm`` (initial state P0, host array in the generator
     layout): from the cache when present, else timed on a scratch copy and

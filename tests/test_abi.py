@@ -143,3 +143,19 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.lib.grmhd_get_tiles(None, 0, ctypes.byref(tx), ctypes.byref(ty)) == lib.GRMHD_EINVAL
     assert lib.lib.grmhd_profile(None, 1) == lib.GRMHD_EINVAL
     assert lib.lib.grmhd_step(None, None, 0.1, None) == lib.GRMHD_EINVAL
+
+
+def test_context_bytes_without_a_device(lib):
+    prm, _ = problems.fm_torus(n1=64, n2=32, n3=16)
+    cb, sb = lib.grmhd_context_bytes(prm)
+    n1p = -(-(64 + 6) // 8) * 8
+    cells = (16 + 6) * (32 + 6) * n1p
+    assert sb == 8 * 8 * cells
+    tables = (64 + 2 * 22) * 8 * (32 + 6) * n1p + 3 * 22 * 4 * (32 + 6) * n1p
+    assert cb > tables + sb + 3 * sb                    # half-step state + three fp64 flux arrays
+    prm_m = dict(prm, precision=problems.MIXED)
+    cbm, sbm = lib.grmhd_context_bytes(prm_m)
+    assert sbm == sb and cb - cbm == 3 * 8 * cells * 4  # fluxes in float
+    bad = dict(prm, n1=0)
+    with pytest.raises(lib.GrmhdError):
+        lib.grmhd_context_bytes(bad)

@@ -84,3 +84,21 @@ def test_tuning_returns_a_candidate_and_caches_it(lib, tmp_path):
     assert sim.get_tiles("sweep") == tiles["sweep"]
     assert sim.get_tiles("update") == tiles["update"]
     sim.close()
+
+
+def test_search_finds_the_separable_minimum():
+    # cost = f(sweep tile) + g(update tile) with distinct minima
+    fs = {(128, 2): 1.0}
+    gs = {(32, 8): 0.5}
+    calls = []
+
+    def measure(t):
+        calls.append(t)
+        return fs.get(t["sweep"], 3.0) + gs.get(t["update"], 2.0)
+
+    tiles, best = tune.search(measure, repeats=2)
+    assert tiles == {"sweep": (128, 2), "update": (32, 8)}
+    assert best == {"sweep": 3.0, "update": 1.5}
+    assert len(calls) == 2 * 2 * len(tune.candidates())
+    # the default is tried first in each class
+    assert calls[0] == {"sweep": (64, 4), "update": (64, 4)}
