@@ -264,6 +264,9 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
   c->up.dx1 = c->dx[0];
   c->up.dx2 = c->dx[1];
   c->up.dx3 = c->dx[2];
+  c->up.idx1 = 1.0 / c->dx[0];
+  c->up.idx2 = 1.0 / c->dx[1];
+  c->up.idx3 = 1.0 / c->dx[2];
   c->up.floors = p->floors ? 1 : 0;
   c->up.polar_lo = p->bc[1][0] == GRMHD_BC_POLAR;
   c->up.polar_hi = p->bc[1][1] == GRMHD_BC_POLAR;

@@ -28,6 +28,7 @@ struct UpdateParams {
   double gam;
   double sigma_max, beta_min, uorho_max, gamma_max;
   double dx1, dx2, dx3;
+  double idx1, idx2, idx3;  // 1 / dx_d
   int floors;
   int polar_lo, polar_hi;  // x2 boundaries are polar axes
 };

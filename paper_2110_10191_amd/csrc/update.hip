@@ -63,17 +63,24 @@ __device__ bool invert_1dw(const double* U, const double* guess, const Geo<doubl
   double x = (guess[0] + gam * guess[1]) * lorentz_sq(g.gcov, guess[2], guess[3], guess[4]) - D;
   int extra = -1;
   for (int it = 0; it < INV_MAXIT && extra < INV_EXTRA; ++it) {
+    // three divisions per iteration: 1/(W bw) gives 1/W and 1/bw,
+    // 1/(s (1 + s)) gives 1/s and 1/(1 + s), and the Newton quotient
     const double W = x + D;
     const double W2 = W * W, bw = bsq + W;
-    const double v2raw = (qtsq * W2 + qdb2 * (bsq + 2.0 * W)) / (bw * bw * W2);
+    const double rwb = 1.0 / (W * bw);
+    const double iW = bw * rwb, ibw = W * rwb;
+    const double iW2 = iW * iW, ibw2 = ibw * ibw;
+    const double v2raw = (qtsq * W2 + qdb2 * (bsq + 2.0 * W)) * (ibw2 * iW2);
     const double v2 = fmin(fmax(v2raw, 0.0), V2MAX);
     const double s = sqrt(1.0 - v2);
-    const double wmr = x * (1.0 - v2) - D * s * v2 / (1.0 + s);
-    const double f = qn_d + x - gf * wmr + 0.5 * bsq * (1.0 + v2) - 0.5 * qdb2 / W2;
-    double dv2 = -2.0 * (qtsq * W2 * W + qdb2 * (3.0 * W2 + 3.0 * W * bsq + bsq * bsq)) / (bw * bw * bw * W2 * W);
+    const double rs = 1.0 / (s * (1.0 + s));
+    const double is = (1.0 + s) * rs, i1s = s * rs;
+    const double wmr = x * (1.0 - v2) - D * s * v2 * i1s;
+    const double f = qn_d + x - gf * wmr + 0.5 * bsq * (1.0 + v2) - 0.5 * qdb2 * iW2;
+    double dv2 = -2.0 * (qtsq * W2 * W + qdb2 * (3.0 * W2 + 3.0 * W * bsq + bsq * bsq)) * (ibw2 * ibw * iW2 * iW);
     if (v2raw > V2MAX || v2raw < 0.0) dv2 = 0.0;
-    const double dp = gf * ((1.0 - v2) + (-W + D / (2.0 * s)) * dv2);
-    const double df = 1.0 - dp + 0.5 * bsq * dv2 + qdb2 / (W2 * W);
+    const double dp = gf * ((1.0 - v2) + (-W + 0.5 * D * is) * dv2);
+    const double df = 1.0 - dp + 0.5 * bsq * dv2 + qdb2 * (iW2 * iW);
     const double dx = -f / df;
     double xn = x + dx;
     if (xn + D <= 0.0) xn = 0.5 * (x + D) - D;
@@ -93,10 +100,10 @@ __device__ bool invert_1dw(const double* U, const double* guess, const Geo<doubl
   const double lor = 1.0 / s;
   P[0] = D * s;
   P[1] = (x * (1.0 - v2c) - D * s * v2c / (1.0 + s)) / gam;
-  const double fac = lor / bw;
-  P[2] = fac * (qt1 + qdb * B1 / W);
-  P[3] = fac * (qt2 + qdb * B2 / W);
-  P[4] = fac * (qt3 + qdb * B3 / W);
+  const double fac = lor / bw, qw = qdb / W;
+  P[2] = fac * (qt1 + qw * B1);
+  P[3] = fac * (qt2 + qw * B2);
+  P[4] = fac * (qt3 + qw * B3);
   P[5] = Bu1;
   P[6] = Bu2;
   P[7] = Bu3;
@@ -157,8 +164,8 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
     for (int v = 0; v < 5; ++v) {
       const double f2m = pl ? 0.0 : F2.at(v, c);
       const double f2p = ph ? 0.0 : F2.at(v, c + s2);
-      rhs[v] = -((F1.at(v, c + s1) - F1.at(v, c)) / up.dx1 + (f2p - f2m) / up.dx2 +
-                 (F3.at(v, c + s3) - F3.at(v, c)) / up.dx3);
+      rhs[v] = -((F1.at(v, c + s1) - F1.at(v, c)) * up.idx1 + (f2p - f2m) * up.idx2 +
+                 (F3.at(v, c + s3) - F3.at(v, c)) * up.idx3);
     }
     // Flux-CT: edge EMFs (in the flux precision)
     const TF q = TF(0.25), h = TF(0.5);
@@ -191,9 +198,9 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
       const double f2b3m = (double)(h * (e1_00 + e1_01)), f2b3p = (double)(h * (e1_10 + e1_11));
       const double f3b1m = (double)(h * (e2_00 + e2_10)), f3b1p = (double)(h * (e2_01 + e2_11));
       const double f3b2m = (double)(-h * (e1_00 + e1_10)), f3b2p = (double)(-h * (e1_01 + e1_11));
-      rhs[5] = -((0.0 - 0.0) / up.dx1 + (f2b1p - f2b1m) / up.dx2 + (f3b1p - f3b1m) / up.dx3);
-      rhs[6] = -((f1b2p - f1b2m) / up.dx1 + (0.0 - 0.0) / up.dx2 + (f3b2p - f3b2m) / up.dx3);
-      rhs[7] = -((f1b3p - f1b3m) / up.dx1 + (f2b3p - f2b3m) / up.dx2 + (0.0 - 0.0) / up.dx3);
+      rhs[5] = -((f2b1p - f2b1m) * up.idx2 + (f3b1p - f3b1m) * up.idx3);
+      rhs[6] = -((f1b2p - f1b2m) * up.idx1 + (f3b2p - f3b2m) * up.idx3);
+      rhs[7] = -((f1b3p - f1b3m) * up.idx1 + (f2b3p - f2b3m) * up.idx2);
     }
 
     const int toff = tab_of(d, j, i);
