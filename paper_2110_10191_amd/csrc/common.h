@@ -216,7 +216,11 @@ __device__ inline T mc_slope(T pm, T p0, T pp) {
 }
 
 // Value at the right edge of the middle zone of (x1..x5), point-value WENO5
-// with Jiang-Shu smoothness indicators and linear weights (1/16, 5/8, 5/16).
+// with Jiang-Shu smoothness indicators and linear weights (1/16, 5/8, 5/16):
+// weights d_k / (eps + b_k)^2, normalised. Written over a common denominator,
+// scaled by the smallest e_k = eps + b_k so nothing leaves the double range:
+// with r_k = e_k / e_min >= 1, the weights are proportional to d_k times the
+// product of the other two r_j^2 (two divisions instead of four).
 __device__ inline double weno5_edge(double x1, double x2, double x3, double x4, double x5) {
   const double q0 = 0.375 * x1 - 1.25 * x2 + 1.875 * x3;
   const double q1 = -0.125 * x2 + 0.75 * x3 + 0.375 * x4;
@@ -224,18 +228,21 @@ __device__ inline double weno5_edge(double x1, double x2, double x3, double x4, 
   const double t0 = x1 - 2.0 * x2 + x3, u0 = x1 - 4.0 * x2 + 3.0 * x3;
   const double t1 = x2 - 2.0 * x3 + x4, u1 = x2 - x4;
   const double t2 = x3 - 2.0 * x4 + x5, u2 = 3.0 * x3 - 4.0 * x4 + x5;
-  const double b0 = (13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0;
-  const double b1 = (13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1;
-  const double b2 = (13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2;
-  const double e0 = 1e-26 + b0, e1 = 1e-26 + b1, e2 = 1e-26 + b2;
-  const double a0 = 0.0625 / (e0 * e0);
-  const double a1 = 0.625 / (e1 * e1);
-  const double a2 = 0.3125 / (e2 * e2);
+  const double e0 = 1e-26 + ((13.0 / 12.0) * t0 * t0 + 0.25 * u0 * u0);
+  const double e1 = 1e-26 + ((13.0 / 12.0) * t1 * t1 + 0.25 * u1 * u1);
+  const double e2 = 1e-26 + ((13.0 / 12.0) * t2 * t2 + 0.25 * u2 * u2);
+  const double im = 1.0 / fmin(fmin(e0, e1), e2);
+  // r_k <= 1e60 keeps the products of two squares finite; such a weight is 0 anyway
+  const double r0 = fmin(e0 * im, 1e60), r1 = fmin(e1 * im, 1e60), r2 = fmin(e2 * im, 1e60);
+  const double s0 = r0 * r0, s1 = r1 * r1, s2 = r2 * r2;
+  const double a0 = 0.0625 * (s1 * s2), a1 = 0.625 * (s0 * s2), a2 = 0.3125 * (s0 * s1);
   return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
-// FP32 form: the weights as w_k = d_k / sum_j d_j ((eps+b_k)/(eps+b_j))^2, which
-// never squares eps (1e-52 is below the float range).
+// FP32 form: eps^2 = 1e-52 is below the float range, so the weights use the
+// ratios r_k = e_min / e_k in (0, 1]: d_k r_k^2, normalised; the term of the
+// smallest e_k has r = 1, so the sum is at least 1/16. Reciprocals by the
+// hardware rcp (about 1 ulp), far below the float rounding of the inputs.
 __device__ inline float weno5_edge(float x1, float x2, float x3, float x4, float x5) {
   const float q0 = 0.375f * x1 - 1.25f * x2 + 1.875f * x3;
   const float q1 = -0.125f * x2 + 0.75f * x3 + 0.375f * x4;
@@ -246,11 +253,11 @@ __device__ inline float weno5_edge(float x1, float x2, float x3, float x4, float
   const float e0 = 1e-26f + ((13.0f / 12.0f) * t0 * t0 + 0.25f * u0 * u0);
   const float e1 = 1e-26f + ((13.0f / 12.0f) * t1 * t1 + 0.25f * u1 * u1);
   const float e2 = 1e-26f + ((13.0f / 12.0f) * t2 * t2 + 0.25f * u2 * u2);
-  const float r01 = e0 / e1, r02 = e0 / e2, r12 = e1 / e2;
-  const float w0 = 0.0625f / (0.0625f + 0.625f * r01 * r01 + 0.3125f * r02 * r02);
-  const float w1 = 0.625f / (0.0625f / (r01 * r01) + 0.625f + 0.3125f * r12 * r12);
-  const float w2 = 1.0f - w0 - w1;
-  return w0 * q0 + w1 * q1 + w2 * q2;
+  const float m = fminf(fminf(e0, e1), e2);
+  const float r0 = m * __builtin_amdgcn_rcpf(e0), r1 = m * __builtin_amdgcn_rcpf(e1),
+              r2 = m * __builtin_amdgcn_rcpf(e2);
+  const float a0 = 0.0625f * r0 * r0, a1 = 0.625f * r1 * r1, a2 = 0.3125f * r2 * r2;
+  return (a0 * q0 + a1 * q1 + a2 * q2) * __builtin_amdgcn_rcpf(a0 + a1 + a2);
 }
 
 // ---------------------------------------------------------------------------

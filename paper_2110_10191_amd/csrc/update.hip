@@ -250,10 +250,12 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
   block_count_to(failed, &ctr->fail, &ctr->fail_total);
 }
 
-// (256, 2): at least two waves per SIMD, i.e. at most 256 registers a lane;
-// left free, the float-flux variant takes a few more and drops to one wave.
+// (256, 3): at least three waves per SIMD, i.e. at most 168 registers a lane.
+// Left free the compiler takes 224 (two waves) and the kernel waits on its
+// loads and long dependency chains with too little to switch to; the FP64
+// variant fits 168 without spilling.
 template <typename TF>
-__global__ __launch_bounds__(256, 2) void update_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
+__global__ __launch_bounds__(256, 3) void update_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
                                                      const TF* __restrict__ F1, const TF* __restrict__ F2,
                                                      const TF* __restrict__ F3, const double* Pb,
                                                      const double* __restrict__ Ps, double* Pout,
@@ -263,7 +265,7 @@ __global__ __launch_bounds__(256, 2) void update_kernel(Dims d, const double* __
 
 // every job of a batch: predictor P -> P_h with dt/2, corrector (P, P_h) -> P with dt
 template <typename TF>
-__global__ __launch_bounds__(256, 2) void update_batch_kernel(BatchView bv, int corrector) {
+__global__ __launch_bounds__(256, 3) void update_batch_kernel(BatchView bv, int corrector) {
   const int* offs = bv.offs + PH_UPDATE * (bv.njobs + 1);
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
