@@ -58,10 +58,29 @@ def algorithmic_bytes(kernel, prm, mixed):
         return 64 * cells + 8 * fb * faces + geo
     if kernel == "update":
         zones = n1 * n2 * n3
-        # 7 flux components per direction (5 hydro + 2 transverse B), P_base, P_s
-        # read, P_out written, one flag byte; the 2D centre table once
-        return zones * (21 * fb + 64 + 64 + 64 + 1) + 64 * 8 * n1 * n2
+        # 7 flux components per direction (5 hydro + 2 transverse B); the states
+        # read: one in the predictor (P_base = P_s = P), two in the corrector
+        # (P, P_h), 96 B a zone on average over the two launches of a step;
+        # P_out written; one flag byte; the 2D centre table once
+        return zones * (21 * fb + 96 + 64 + 1) + 64 * 8 * n1 * n2
     raise KeyError(kernel)
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of ``kernel`` from the committed counter summary
+    (profiles/hbm_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a plain
+    copy), only while the library is the build those counters were taken on."""
+    path = os.path.join(HERE, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        from paper_2110_10191_amd import tune
+        if (rec.get("kernel") == kernel and rec.get("workload") == workload
+                and rec.get("library_hash") == tune.library_hash()):
+            return float(rec["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
 
 
 def cpu_baseline(prm_full, nslabs=8):
@@ -253,8 +272,10 @@ def main():
     ms, n = kernels[dom]
     per_launch = algorithmic_bytes(dom, prm, mixed)
     achieved = per_launch / (ms / n / 1e3)
+    workload = f"fm_torus_{n1}x{n2}x{n3}_{args.recon}_{args.precision}"
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None, "kernel": dom,
+                "frac": achieved / HBM_PEAK, "traffic": measured_traffic(dom, workload),
+                "traffic_unit": "bytes per launch", "kernel": dom,
                 "algorithmic_bytes_per_launch": per_launch, "mean_launch_ms": ms / n}
 
     if args.copy_calibration_gib > 0:
@@ -278,7 +299,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if not mixed else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"fm_torus_{n1}x{n2}x{n3}_{args.recon}_{args.precision}",
+        "config": {"workload": workload,
                    "grid": [n1, n2, n3], "a": prm["a"], "recon": args.recon,
                    "precision": args.precision, "coords": "fmks", "r_out": 1000.0},
         "roofline": roofline,

@@ -231,7 +231,7 @@ class Server:
     """
 
     def __init__(self, engine, make_state, budget_bytes, clock=None, quantum=25, prefetch=8,
-                 keep=()):
+                 keep=(), progress=None):
         self.engine = engine
         self.make_state = make_state
         self.budget = budget_bytes
@@ -239,6 +239,7 @@ class Server:
         self.quantum = max(1, int(quantum))
         self.prefetch = max(1, int(prefetch))
         self.keep = set(keep)
+        self.progress = progress            # progress(server, now, running, queued, done) per cycle
         self.in_use = 0
         self.peak_in_use = 0
         self.max_running = 0
@@ -311,6 +312,9 @@ class Server:
                     r.done = now
                     self.in_use -= r.bytes
                     del running[r.spec.id]
+            if self.progress:
+                self.progress(self, now, len(running), len(queue),
+                              sum(1 for r in recs if r.done is not None))
         return Report(recs, rejected, self)
 
 
@@ -412,9 +416,20 @@ def main(argv=None):
     rng = np.random.default_rng(args.seed + 1000)
     sample = sorted(int(x) for x in rng.choice(len(specs), size=min(args.identity, len(specs)), replace=False))
     eng = GpuEngine(recon, precision, tiles=tiles)
-    srv = Server(eng, make_state, int(args.budget_gb * 1e9), quantum=args.quantum, keep=sample)
+    last = [0.0]
+
+    def progress(srv, now, running, queued, done):
+        if now - last[0] >= 5.0:
+            last[0] = now
+            print(f"[serve] t={now:.1f}s done={done} running={running} queued={queued} "
+                  f"cycles={srv.cycles} bytes={srv.in_use / 1e9:.1f}GB", file=sys.stderr, flush=True)
+
+    srv = Server(eng, make_state, int(args.budget_gb * 1e9), quantum=args.quantum, keep=sample,
+                 progress=progress)
     rep = srv.run(specs)
     summ = rep.summary()
+    print(f"[serve] stream done in {rep.makespan:.1f}s; identity check of {len(sample)} jobs",
+          file=sys.stderr, flush=True)
     ident = identity_check(rep, specs, make_state, recon, precision, sample, tiles=tiles)
     summ["identity_alone_vs_mix"] = {str(k): v for k, v in ident.items()}
     summ["config"] = {"workload": f"poisson stream of {args.jobs} torus/Bondi jobs",
