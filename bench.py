@@ -83,7 +83,7 @@ def measured_traffic(kernel, workload):
     return None
 
 
-def cpu_baseline(prm_full, nslabs=8):
+def cpu_baseline(prm_full, nslabs=16):
     """The oracle on the same torus grid with nslabs x3 slabs, one step."""
     import numpy as np
     import oracle
