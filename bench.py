@@ -10,13 +10,16 @@ LLF fluxes, Flux-CT, predictor-corrector, FP64. Synthetic initial data from
 ``problems.fm_torus``; the state is resident in HBM before timing starts.
 
 A step is one full predictor-corrector cycle of every zone, including the
-Courant step read back each step (dt <- min(dt_next, 1.3 dt)). The metric is
+Courant step for the next one (dt <- min(dt_next, 1.3 dt)). By default the
+steps go through the batch calls with this one job, so the step size stays on
+the device and the host does not wait between steps (``--path host`` instead
+calls grmhd_step once a step and reads dt back each time). The metric is
 zone-cycles per second: interior zones x steps / wall seconds over the timed
 steps (bracketed by device synchronisation). Kernel durations over the same
-timed region come from HIP events the library records on its stream; the
-dominant kernel's algorithmic bytes per launch over its mean duration give the
-roofline fraction against 8 TB/s. The oracle (NumPy FP64, one core) is timed on
-a bounded sample of the same workload.
+timed region come from HIP events the library records on its stream around
+every launch; the dominant kernel's algorithmic bytes per launch over its mean
+duration give the roofline fraction against 8 TB/s. The oracle (NumPy FP64,
+one core) is timed on a bounded sample of the same workload.
 
 Prints one JSON line on stdout.
 """
@@ -83,25 +86,26 @@ def measured_traffic(kernel, workload):
     return None
 
 
-def cpu_baseline(prm_full, nslabs=16):
-    """The oracle on the same torus grid with nslabs x3 slabs, one step."""
-    import numpy as np
+def cpu_baseline(prm_full, nslabs=32, nsteps=2):
+    """The oracle on the same torus grid with nslabs x3 slabs, nsteps steps."""
     import oracle
     import problems
     prm, P0 = problems.fm_torus(n1=prm_full["n1"], n2=prm_full["n2"], n3=nslabs,
                                 recon=prm_full["recon"])
     g = oracle.Grid(prm)
     dt = 0.005
+    P = P0
     t0 = time.perf_counter()
-    oracle.step(P0, g, dt)
+    for _ in range(nsteps):
+        P, _, _ = oracle.step(P, g, dt)
     secs = time.perf_counter() - t0
     zones = prm["n1"] * prm["n2"] * prm["n3"]
     return {
-        "value": zones / secs,
+        "value": zones * nsteps / secs,
         "unit": "zone-cycles/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": (f"1 FP64 step of the {prm['n1']}x{prm['n2']} FMKS torus grid with {nslabs} x3 slabs "
+        "sample": (f"{nsteps} FP64 steps of the {prm['n1']}x{prm['n2']} FMKS torus grid with {nslabs} x3 slabs "
                    f"({zones} zones, same per-zone work as the benchmark grid) in {secs:.1f} s; "
                    "NumPy element-wise, single thread"),
     }
@@ -210,6 +214,9 @@ def main():
     ap.add_argument("--workload", choices=["torus", "many"], default="torus",
                     help="torus: one large torus (default); many: 64 uneven jobs batched vs looped")
     ap.add_argument("--tune", action="store_true", help="autotune the batch tiles (workload many)")
+    ap.add_argument("--path", choices=["device", "host"], default="host",
+                    help="host: one grmhd_step per step with dt read back each step (default); device: "
+                         "steps through the batch calls with the step size kept on the device")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="also run one plain device copy of this size (for counter scaling)")
     args = ap.parse_args()
@@ -243,24 +250,46 @@ def main():
     torch.cuda.synchronize()
 
     dt = sim.get_dt(P)
-    for _ in range(args.warmup):
-        dt = min(sim.step(P, dt), 1.3 * dt)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
-
-    g.grmhd_profile(sim.ctx, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dt = min(sim.step(P, dt), 1.3 * dt)
-    torch.cuda.synchronize()
-    secs = time.perf_counter() - t0
-    g.grmhd_profile(sim.ctx, False)
-
     kernels = {}
-    for name in g.KERNELS:
-        ms, n = g.grmhd_profile_read(sim.ctx, name)
-        kernels[name] = (ms, n)
+    if args.path == "host":
+        # one grmhd_step call per step; dt read back to the host every step
+        for _ in range(args.warmup):
+            dt = min(sim.step(P, dt), 1.3 * dt)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
+        g.grmhd_profile(sim.ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dt = min(sim.step(P, dt), 1.3 * dt)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        g.grmhd_profile(sim.ctx, False)
+        for name in g.KERNELS:
+            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
+    else:
+        # the same kernels through the batch calls with one job: the step size
+        # stays on the device (dt <- min(dt_next, 1.3 dt) by a kernel), so the
+        # host never waits between steps; every launch is bracketed by events
+        b = g.Batch([sim])
+        b.set_dt([dt])
+        b.step([P], nsteps=args.warmup)
+        dts, _ = b.get()
+        print(f"[bench] warmup done, dt = {dts[0]:.3e}", file=sys.stderr, flush=True)
+        b.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.step([P], nsteps=args.steps)
+        dts, status = b.get()
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        for name in g.KERNELS:
+            kernels[name] = b.profile_read(name)
+        b.profile(False)
+        b.close()
+        dt = dts[0]
+        if status[0]:
+            print("[bench] non-finite signal speed in the timed steps", file=sys.stderr, flush=True)
     fails = sim.step_failures()
     divb = sim.divb(P)
     zones = n1 * n2 * n3
@@ -301,7 +330,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload,
                    "grid": [n1, n2, n3], "a": prm["a"], "recon": args.recon,
-                   "precision": args.precision, "coords": "fmks", "r_out": 1000.0},
+                   "precision": args.precision, "coords": "fmks", "r_out": 1000.0,
+                   "driver": args.path},
         "roofline": roofline,
         "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kernels.items()},
         "checks": {"max_divb": divb, "failed_inversions_last_step": fails, "dt": dt},

@@ -197,6 +197,13 @@ GRMHD_API int grmhd_batch_get(grmhd_batch *b, double *dt, int32_t *status);
  * from the previous call the job table is re-uploaded and the step graph
  * re-captured (synchronises once); otherwise asynchronous. */
 GRMHD_API int grmhd_batch_step(grmhd_batch *b, double *const *P, const int32_t *active, int32_t nsteps);
+/* Kernel timing of batch steps, as grmhd_profile / grmhd_profile_read for a
+ * context (same kernel classes, each launch spanning every active job). While
+ * profiling is on, grmhd_batch_step enqueues its launches directly, each
+ * bracketed by two events, instead of replaying the captured graph: the same
+ * kernels in the same order, so results are unchanged. */
+GRMHD_API int grmhd_batch_profile(grmhd_batch *b, int32_t enable);
+GRMHD_API int grmhd_batch_profile_read(grmhd_batch *b, int32_t kernel, double *total_ms, int64_t *launches);
 GRMHD_API int grmhd_batch_free(grmhd_batch *b);
 GRMHD_API const char *grmhd_batch_last_error(const grmhd_batch *b);
 

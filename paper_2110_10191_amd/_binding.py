@@ -17,7 +17,7 @@ EXPORTED = [
     "grmhd_get_dt", "grmhd_step", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
-    "grmhd_batch_free", "grmhd_batch_last_error",
+    "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
 ]
 KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5}
 TILES = {"sweep": 0, "update": 1}
@@ -93,6 +93,8 @@ def _load():
         "grmhd_batch_get": ([vp, dp, ctypes.POINTER(i32)], ctypes.c_int),
         "grmhd_batch_step": ([vp, ctypes.POINTER(vp), ctypes.POINTER(i32), i32], ctypes.c_int),
         "grmhd_batch_free": ([vp], ctypes.c_int),
+        "grmhd_batch_profile": ([vp, i32], ctypes.c_int),
+        "grmhd_batch_profile_read": ([vp, i32, dp, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_batch_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -266,6 +268,19 @@ def grmhd_batch_step(b, states, active=None, nsteps=1):
     _bcheck(lib.grmhd_batch_step(b, ptrs, act, int(nsteps)), b)
 
 
+def grmhd_batch_profile(b, enable):
+    _bcheck(lib.grmhd_batch_profile(b, 1 if enable else 0), b)
+
+
+def grmhd_batch_profile_read(b, kernel):
+    """(total ms, launches) of one kernel class over batch steps since profiling began."""
+    k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _bcheck(lib.grmhd_batch_profile_read(b, k, ctypes.byref(ms), ctypes.byref(n)), b)
+    return ms.value, n.value
+
+
 def grmhd_batch_free(b):
     _bcheck(lib.grmhd_batch_free(b))
 
@@ -289,6 +304,12 @@ class Batch:
 
     def step(self, states, active=None, nsteps=1):
         grmhd_batch_step(self.b, states, active, nsteps)
+
+    def profile(self, enable):
+        grmhd_batch_profile(self.b, enable)
+
+    def profile_read(self, kernel):
+        return grmhd_batch_profile_read(self.b, kernel)
 
     def close(self):
         if self.b:

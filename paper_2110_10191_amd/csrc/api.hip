@@ -114,70 +114,29 @@ hipError_t dalloc(T** ptr, size_t bytes) {
   return hipMalloc((void**)ptr, bytes);
 }
 
-hipEvent_t pooled_event(grmhd_ctx* c) {
-  if (!c->event_pool.empty()) {
-    hipEvent_t e = c->event_pool.back();
-    c->event_pool.pop_back();
-    return e;
-  }
-  hipEvent_t e = nullptr;
-  if (hipEventCreate(&e) != hipSuccess) return nullptr;
-  return e;
-}
-
-// brackets one launch with events when profiling is on
-struct ProfScope {
-  grmhd_ctx* c;
-  ProfRecord r{};
-  bool on;
-  ProfScope(grmhd_ctx* ctx, int kernel) : c(ctx), on(ctx->profiling) {
-    if (!on) return;
-    r.kernel = kernel;
-    r.start = pooled_event(c);
-    r.stop = pooled_event(c);
-    if (!r.start || !r.stop) {
-      on = false;
-      return;
-    }
-    (void)hipEventRecord(r.start, c->stream);
-  }
-  ~ProfScope() {
-    if (!on) return;
-    (void)hipEventRecord(r.stop, c->stream);
-    c->prof.push_back(r);
-  }
-};
-
-void clear_profile(grmhd_ctx* c) {
-  for (auto& r : c->prof) {
-    c->event_pool.push_back(r.start);
-    c->event_pool.push_back(r.stop);
-  }
-  c->prof.clear();
-}
 
 // predictor or corrector substep; dsrc is the base state (source of Dirichlet ghosts)
 int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop) {
   hipStream_t s = c->stream;
   {
-    ProfScope ps(c, GRMHD_K_GHOSTS);
+    ProfScope ps(c->prof, s, GRMHD_K_GHOSTS);
     HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s), "ghost fill");
   }
   HIP_OR_FAIL(c, launch_reset(c->ctr, want_ctop ? (1 | 4) : 4, s), "reset");
   for (int dir = 1; dir <= 3; ++dir) {
-    ProfScope ps(c, GRMHD_K_SWEEP1 + dir - 1);
+    ProfScope ps(c->prof, s, GRMHD_K_SWEEP1 + dir - 1);
     HIP_OR_FAIL(c, launch_sweep(dir, c->p.recon, c->mixed, c->d, c->t, c->p.gam, Ps, c->F[dir - 1],
                                 want_ctop ? c->ctr->ctop : nullptr, s),
                 "sweep");
   }
   {
-    ProfScope ps(c, GRMHD_K_UPDATE);
+    ProfScope ps(c->prof, s, GRMHD_K_UPDATE);
     HIP_OR_FAIL(c, launch_update(c->mixed, c->d, c->t, c->up, c->F[0], c->F[1], c->F[2], Pb, Ps, Pout,
                                  c->flags, dt, c->ctr, s),
                 "update");
   }
   {
-    ProfScope ps(c, GRMHD_K_FIXUP);
+    ProfScope ps(c->prof, s, GRMHD_K_FIXUP);
     HIP_OR_FAIL(c, launch_fixup(c->d, c->t, c->up, Pout, c->flags, c->ctr, s), "fixup");
   }
   return GRMHD_OK;
@@ -311,8 +270,7 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
 int grmhd_free(grmhd_ctx* ctx) {
   if (!ctx) return GRMHD_OK;
   (void)hipStreamSynchronize(ctx->stream);
-  clear_profile(ctx);
-  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  ctx->prof.destroy();
   free_all(ctx);
   delete ctx;
   return GRMHD_OK;
@@ -353,9 +311,9 @@ int grmhd_profile(grmhd_ctx* ctx, int32_t enable) {
   if (!ctx) return GRMHD_EINVAL;
   if (enable) {
     HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
-    clear_profile(ctx);
+    ctx->prof.clear();
   }
-  ctx->profiling = enable != 0;
+  ctx->prof.on = enable != 0;
   return GRMHD_OK;
 }
 
@@ -363,17 +321,7 @@ int grmhd_profile_read(grmhd_ctx* ctx, int32_t kernel, double* total_ms, int64_t
   if (!ctx || !total_ms || !launches) return GRMHD_EINVAL;
   if (kernel < 0 || kernel >= GRMHD_K_COUNT) return fail(ctx, GRMHD_EINVAL, "profile_read: unknown kernel");
   HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
-  double sum = 0.0;
-  int64_t n = 0;
-  for (const auto& r : ctx->prof) {
-    if (r.kernel != kernel) continue;
-    float ms = 0.0f;
-    HIP_OR_FAIL(ctx, hipEventElapsedTime(&ms, r.start, r.stop), "event time");
-    sum += ms;
-    ++n;
-  }
-  *total_ms = sum;
-  *launches = n;
+  HIP_OR_FAIL(ctx, ctx->prof.total(kernel, total_ms, launches), "event time");
   return GRMHD_OK;
 }
 

@@ -33,6 +33,7 @@ struct grmhd_batch {
   int stx = TILE_X, sty = TILE_Y, utx = TILE_X, uty = TILE_Y;  // tiles of every job
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  Profiler prof;  // when on, steps run eagerly with each launch bracketed by events
   std::string err;
 };
 
@@ -59,19 +60,34 @@ void drop_graph(grmhd_batch* b) {
   b->graph = nullptr;
 }
 
-// enqueue one step of every job in the current job table
+// enqueue one step of every job in the current job table (events around the
+// launches only when profiling, which never happens under capture)
 hipError_t enqueue_step(grmhd_batch* b) {
   const BatchView bv{b->d_jobs, b->d_offs, b->nactive, b->stx, b->sty, b->utx, b->uty};
+  hipStream_t s = b->stream;
   hipError_t e;
-  if ((e = launch_batch_reset(bv, 8, b->stream)) != hipSuccess) return e;
+  if ((e = launch_batch_reset(bv, 8, s)) != hipSuccess) return e;
   for (int corr = 0; corr < 2; ++corr) {
-    if ((e = launch_batch_ghosts(bv, b->totals, corr == 1, b->stream)) != hipSuccess) return e;
-    if ((e = launch_batch_reset(bv, corr ? (1 | 4) : 4, b->stream)) != hipSuccess) return e;
-    if ((e = launch_batch_sweeps(bv, b->totals, b->recon, b->mixed, corr == 1, corr == 1, b->stream)) != hipSuccess)
-      return e;
-    if ((e = launch_batch_update(bv, b->totals, b->mixed, corr == 1, b->stream)) != hipSuccess) return e;
+    {
+      ProfScope ps(b->prof, s, GRMHD_K_GHOSTS);
+      if ((e = launch_batch_ghosts(bv, b->totals, corr == 1, s)) != hipSuccess) return e;
+    }
+    if ((e = launch_batch_reset(bv, corr ? (1 | 4) : 4, s)) != hipSuccess) return e;
+    for (int dir = 1; dir <= 3; ++dir) {
+      ProfScope ps(b->prof, s, GRMHD_K_SWEEP1 + dir - 1);
+      if ((e = launch_batch_sweeps(bv, b->totals, b->recon, b->mixed, corr == 1, corr == 1, dir, s)) != hipSuccess)
+        return e;
+    }
+    {
+      ProfScope ps(b->prof, s, GRMHD_K_UPDATE);
+      if ((e = launch_batch_update(bv, b->totals, b->mixed, corr == 1, 1, s)) != hipSuccess) return e;
+    }
+    {
+      ProfScope ps(b->prof, s, GRMHD_K_FIXUP);
+      if ((e = launch_batch_update(bv, b->totals, b->mixed, corr == 1, 2, s)) != hipSuccess) return e;
+    }
   }
-  return launch_batch_dt(bv, b->stream);
+  return launch_batch_dt(bv, s);
 }
 
 int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
@@ -128,7 +144,10 @@ int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
   BHIP(b, hipMemcpy(b->d_jobs, jobs.data(), sizeof(JobDesc) * na, hipMemcpyHostToDevice), "upload jobs");
   BHIP(b, hipMemcpy(b->d_offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice), "upload offsets");
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
+  const bool prof_on = b->prof.on;
+  b->prof.on = false;
   hipError_t e = enqueue_step(b);
+  b->prof.on = prof_on;
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(b->stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
@@ -228,7 +247,29 @@ int grmhd_batch_step(grmhd_batch* b, double* const* P, const int32_t* active, in
     if (st != GRMHD_OK) return st;
   }
   if (b->nactive == 0) return GRMHD_OK;
+  if (b->prof.on) {
+    for (int s = 0; s < nsteps; ++s) BHIP(b, enqueue_step(b), "step");
+    return GRMHD_OK;
+  }
   for (int s = 0; s < nsteps; ++s) BHIP(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
+  return GRMHD_OK;
+}
+
+int grmhd_batch_profile(grmhd_batch* b, int32_t enable) {
+  if (!b) return GRMHD_EINVAL;
+  if (enable) {
+    BHIP(b, hipStreamSynchronize(b->stream), "synchronize");
+    b->prof.clear();
+  }
+  b->prof.on = enable != 0;
+  return GRMHD_OK;
+}
+
+int grmhd_batch_profile_read(grmhd_batch* b, int32_t kernel, double* total_ms, int64_t* launches) {
+  if (!b || !total_ms || !launches) return GRMHD_EINVAL;
+  if (kernel < 0 || kernel >= GRMHD_K_COUNT) return bfail(b, GRMHD_EINVAL, "profile_read: unknown kernel");
+  BHIP(b, hipStreamSynchronize(b->stream), "synchronize");
+  BHIP(b, b->prof.total(kernel, total_ms, launches), "event time");
   return GRMHD_OK;
 }
 
@@ -236,6 +277,7 @@ int grmhd_batch_free(grmhd_batch* b) {
   if (!b) return GRMHD_OK;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   drop_graph(b);
+  b->prof.destroy();
   void* ptrs[] = {b->d_jobs, b->d_offs, b->d_dt, b->d_status};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);

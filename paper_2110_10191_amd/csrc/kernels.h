@@ -78,9 +78,12 @@ void job_phase_blocks(const Dims& d, int counts[PH_COUNT]);
 // corrector = true: ghosts of P_h, fluxes of P_h, (P, P_h) -> P with dt.
 // totals[ph] = grid size of phase ph over the batch.
 hipError_t launch_batch_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s);
+// dir 1..3: one direction; 0: all three
 hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon, bool mixed, bool corrector,
-                               bool want_ctop, hipStream_t s);
-hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, hipStream_t s);
+                               bool want_ctop, int dir, hipStream_t s);
+// which: 1 the update, 2 the fixup, 3 both
+hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, int which,
+                               hipStream_t s);
 hipError_t launch_batch_reset(const BatchView& bv, int mask, hipStream_t s);
 // dt <- min(cfl / sum_d(ctop_d / dx_d), 1.3 dt) per job, on the device
 hipError_t launch_batch_dt(const BatchView& bv, hipStream_t s);

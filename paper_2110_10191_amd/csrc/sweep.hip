@@ -131,13 +131,18 @@ void launch_dir(int dir, const Dims& d, const T* cent, const T* f1, const T* f2,
   else launch_one<3, RECON, T>(d, cent, gam, P, F, ctop, s);
 }
 
+// dir 1..3: that direction only; 0: all three
 template <int RECON, typename T>
-void launch_batch_dirs(const BatchView& bv, const int* totals, bool corrector, bool want_ctop, hipStream_t s) {
+void launch_batch_dirs(const BatchView& bv, const int* totals, bool corrector, bool want_ctop, int dir,
+                       hipStream_t s) {
   const dim3 blk(bv.stx, bv.sty, 1);
   const int c = corrector ? 1 : 0, w = want_ctop ? 1 : 0;
-  hipLaunchKernelGGL((sweep_batch_kernel<1, RECON, T>), dim3(totals[PH_SWEEP1]), blk, 0, s, bv, c, w);
-  hipLaunchKernelGGL((sweep_batch_kernel<2, RECON, T>), dim3(totals[PH_SWEEP2]), blk, 0, s, bv, c, w);
-  hipLaunchKernelGGL((sweep_batch_kernel<3, RECON, T>), dim3(totals[PH_SWEEP3]), blk, 0, s, bv, c, w);
+  if (dir == 0 || dir == 1)
+    hipLaunchKernelGGL((sweep_batch_kernel<1, RECON, T>), dim3(totals[PH_SWEEP1]), blk, 0, s, bv, c, w);
+  if (dir == 0 || dir == 2)
+    hipLaunchKernelGGL((sweep_batch_kernel<2, RECON, T>), dim3(totals[PH_SWEEP2]), blk, 0, s, bv, c, w);
+  if (dir == 0 || dir == 3)
+    hipLaunchKernelGGL((sweep_batch_kernel<3, RECON, T>), dim3(totals[PH_SWEEP3]), blk, 0, s, bv, c, w);
 }
 
 }  // namespace
@@ -159,13 +164,13 @@ hipError_t launch_sweep(int dir, int recon, bool mixed, const Dims& d, const Tab
 }
 
 hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon, bool mixed, bool corrector,
-                               bool want_ctop, hipStream_t s) {
+                               bool want_ctop, int dir, hipStream_t s) {
   if (mixed) {
-    if (recon == GRMHD_RECON_MC) launch_batch_dirs<GRMHD_RECON_MC, float>(bv, totals, corrector, want_ctop, s);
-    else launch_batch_dirs<GRMHD_RECON_WENO5, float>(bv, totals, corrector, want_ctop, s);
+    if (recon == GRMHD_RECON_MC) launch_batch_dirs<GRMHD_RECON_MC, float>(bv, totals, corrector, want_ctop, dir, s);
+    else launch_batch_dirs<GRMHD_RECON_WENO5, float>(bv, totals, corrector, want_ctop, dir, s);
   } else {
-    if (recon == GRMHD_RECON_MC) launch_batch_dirs<GRMHD_RECON_MC, double>(bv, totals, corrector, want_ctop, s);
-    else launch_batch_dirs<GRMHD_RECON_WENO5, double>(bv, totals, corrector, want_ctop, s);
+    if (recon == GRMHD_RECON_MC) launch_batch_dirs<GRMHD_RECON_MC, double>(bv, totals, corrector, want_ctop, dir, s);
+    else launch_batch_dirs<GRMHD_RECON_WENO5, double>(bv, totals, corrector, want_ctop, dir, s);
   }
   return hipGetLastError();
 }

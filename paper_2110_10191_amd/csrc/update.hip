@@ -390,12 +390,15 @@ hipError_t launch_fixup(const Dims& d, const Tables& t, const UpdateParams& up, 
   return hipGetLastError();
 }
 
-hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, hipStream_t s) {
+hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, int which,
+                               hipStream_t s) {
   const dim3 blk(bv.utx, bv.uty, 1), grd(totals[PH_UPDATE]);
   const int c = corrector ? 1 : 0;
-  if (mixed) hipLaunchKernelGGL(update_batch_kernel<float>, grd, blk, 0, s, bv, c);
-  else hipLaunchKernelGGL(update_batch_kernel<double>, grd, blk, 0, s, bv, c);
-  hipLaunchKernelGGL(fixup_batch_kernel, grd, blk, 0, s, bv, c);
+  if (which & 1) {
+    if (mixed) hipLaunchKernelGGL(update_batch_kernel<float>, grd, blk, 0, s, bv, c);
+    else hipLaunchKernelGGL(update_batch_kernel<double>, grd, blk, 0, s, bv, c);
+  }
+  if (which & 2) hipLaunchKernelGGL(fixup_batch_kernel, grd, blk, 0, s, bv, c);
   return hipGetLastError();
 }
 

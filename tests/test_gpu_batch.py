@@ -141,3 +141,33 @@ def test_inactive_jobs_untouched(lib):
         assert np.array_equal(interior(outs[j], prm), interior(P0, prm))
     full, _, _ = run_batch(lib, [jobs[0], jobs[2]], 3)
     assert np.array_equal(outs[0], full[0]) and np.array_equal(outs[2], full[1])
+
+
+def test_profiled_batch_steps_equal_graph_replays(lib):
+    """With profiling on, batch steps run as direct launches with events; the
+    results equal the captured-graph replays bit for bit, and every phase is
+    timed once per substep."""
+    prm, P0 = problems.fm_torus(n1=48, n2=28, n3=4)
+    outs = []
+    for prof in (False, True):
+        sim = lib.Sim(prm)
+        P = sim.to_device(P0)
+        dt = sim.get_dt(P)
+        b = lib.Batch([sim])
+        b.set_dt([dt])
+        b.step([P], nsteps=1)                 # captures the graph
+        if prof:
+            b.profile(True)
+        b.step([P], nsteps=3)
+        dts, status = b.get()
+        assert status == [0]
+        if prof:
+            for name in ("ghosts", "sweep1", "sweep2", "sweep3", "update", "fixup"):
+                ms, n = b.profile_read(name)
+                assert n == 6 and ms > 0.0, name
+            b.profile(False)
+        outs.append((sim.to_host(P), dts[0]))
+        b.close()
+        sim.close()
+    assert outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][0], outs[1][0])
