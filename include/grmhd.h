@@ -164,9 +164,10 @@ GRMHD_API int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_m
 
 /* Thread-block tile of the sweep kernels (GRMHD_TILE_SWEEP) or of the update
  * and fixup kernels (GRMHD_TILE_UPDATE): tx zones along x1 by ty along x2, one
- * thread per zone; tx a power of two in [16, 256], tx * ty a multiple of 64 and
- * at most 256. Default 64 x 4. Results do not depend on the tile. A batch uses
- * the tiles of its first job for every job. */
+ * thread per zone or face; tx a power of two in [16, 256], tx * ty a multiple
+ * of 64 and at most 512 (sweeps) or 256 (update). Defaults: sweeps 64 x 8,
+ * update 64 x 4. Results do not depend on the tile. A batch uses the tiles of
+ * its first job for every job. Errors: EINVAL. */
 enum { GRMHD_TILE_SWEEP = 0, GRMHD_TILE_UPDATE = 1 };
 GRMHD_API int grmhd_set_tiles(grmhd_ctx *ctx, int32_t which, int32_t tx, int32_t ty);
 GRMHD_API int grmhd_get_tiles(const grmhd_ctx *ctx, int32_t which, int32_t *tx, int32_t *ty);

@@ -98,7 +98,8 @@ Dims make_dims(const grmhd_problem& p) {
   d.sv = d.p3 * d.s3;
   d.ts = d.p2 * d.p1;
   d.stx = d.utx = TILE_X;
-  d.sty = d.uty = TILE_Y;
+  d.sty = SWEEP_TILE_Y;
+  d.uty = TILE_Y;
   return d;
 }
 
@@ -279,8 +280,11 @@ int grmhd_free(grmhd_ctx* ctx) {
 int grmhd_set_tiles(grmhd_ctx* ctx, int32_t which, int32_t tx, int32_t ty) {
   if (!ctx) return GRMHD_EINVAL;
   const bool pow2 = tx >= 16 && tx <= 256 && (tx & (tx - 1)) == 0;
-  if (!pow2 || ty < 1 || tx * ty > 256 || (tx * ty) % 64 != 0)
-    return fail(ctx, GRMHD_EINVAL, "set_tiles: need tx a power of two in [16, 256], tx*ty a multiple of 64, <= 256");
+  const int maxt = which == GRMHD_TILE_SWEEP ? SWEEP_MAX_THREADS : UPDATE_MAX_THREADS;
+  if (!pow2 || ty < 1 || tx * ty > maxt || (tx * ty) % 64 != 0)
+    return fail(ctx, GRMHD_EINVAL,
+                "set_tiles: need tx a power of two in [16, 256], tx*ty a multiple of 64, at most 512 "
+                "(sweeps) or 256 (update)");
   if (which == GRMHD_TILE_SWEEP) {
     ctx->d.stx = tx;
     ctx->d.sty = ty;

@@ -30,7 +30,7 @@ struct grmhd_batch {
   std::vector<int32_t> cur_active;
   int totals[PH_COUNT] = {0};
   int nactive = 0;
-  int stx = TILE_X, sty = TILE_Y, utx = TILE_X, uty = TILE_Y;  // tiles of every job
+  int stx = TILE_X, sty = SWEEP_TILE_Y, utx = TILE_X, uty = TILE_Y;  // tiles of every job
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   Profiler prof;  // when on, steps run eagerly with each launch bracketed by events

@@ -88,7 +88,7 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
 }
 
 template <int D, int RECON, typename T>
-__global__ __launch_bounds__(256) void sweep_kernel(Dims d, const double* __restrict__ P, const T* __restrict__ tab,
+__global__ __launch_bounds__(512) void sweep_kernel(Dims d, const double* __restrict__ P, const T* __restrict__ tab,
                                                     T* __restrict__ F, T gam, unsigned long long* ctop) {
   sweep_body<D, RECON, T>(d, P, tab, F, gam, (int)blockIdx.x, ctop);
 }
@@ -106,7 +106,7 @@ __device__ inline const float* face_table<float>(const Tables& t, int dir) {
 
 // every job of a batch in one grid; predictor sweeps P, corrector sweeps P_h
 template <int D, int RECON, typename T>
-__global__ __launch_bounds__(256) void sweep_batch_kernel(BatchView bv, int corrector, int want_ctop) {
+__global__ __launch_bounds__(512) void sweep_batch_kernel(BatchView bv, int corrector, int want_ctop) {
   const int* offs = bv.offs + (PH_SWEEP1 + D - 1) * (bv.njobs + 1);
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];

@@ -30,10 +30,11 @@ import statistics
 
 from . import _binding as B
 
-# x1 tile widths and rows per block; waves per block = tx * ty / 64 in {1, 2, 4}
+# x1 tile widths and rows per block; waves per block = tx * ty / 64
 WIDTHS = (32, 64, 128, 256)
-ROWS = (1, 2, 4, 8)
-MAX_THREADS = 256
+ROWS = (1, 2, 4, 8, 16)
+MAX_THREADS = {"sweep": 512, "update": 256}   # the kernels' launch bounds
+DEFAULT = {"sweep": (64, 8), "update": (64, 4)}
 
 SWEEP_CLASSES = ("sweep1", "sweep2", "sweep3")
 UPDATE_CLASSES = ("update", "fixup")
@@ -41,13 +42,14 @@ UPDATE_CLASSES = ("update", "fixup")
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "grmhd", "tiles.json")
 
 
-def candidates():
-    """Every legal tile of the candidate set: tx * ty a multiple of 64, at most 256."""
+def candidates(cls="update"):
+    """Every legal tile of the candidate set for a kernel class: tx * ty a
+    multiple of 64, at most the class's launch bound."""
     out = []
     for tx in WIDTHS:
         for ty in ROWS:
             n = tx * ty
-            if n % 64 == 0 and n <= MAX_THREADS:
+            if n % 64 == 0 and n <= MAX_THREADS[cls]:
                 out.append((tx, ty))
     return out
 
@@ -117,7 +119,7 @@ class TileCache:
         tiles = {}
         for cls in ("sweep", "update"):
             t = entry.get(cls)
-            if t is None or tuple(t) not in candidates():
+            if t is None or tuple(t) not in candidates(cls):
                 return None
             tiles[cls] = tuple(t)
         return tiles
@@ -148,9 +150,9 @@ def pick(times):
     return best, best_t
 
 
-def _ordered(default):
-    c = candidates()
-    return [default] + [t for t in c if t != default]
+def _ordered(cls, default=None):
+    default = default or DEFAULT[cls]
+    return [default] + [t for t in candidates(cls) if t != default]
 
 
 def time_classes(sim, P, dt, classes, steps, repeats):
@@ -169,7 +171,7 @@ def time_classes(sim, P, dt, classes, steps, repeats):
     return out
 
 
-def tune_sim(sim, P, steps=3, repeats=3, default=(64, 4)):
+def tune_sim(sim, P, steps=3, repeats=3):
     """Time every candidate tile for the sweep and the update classes, each
     starting from state P (restored afterwards), and return
     ({"sweep": t, "update": t}, {"sweep": ms, "update": ms}). Leaves the best
@@ -180,7 +182,7 @@ def tune_sim(sim, P, steps=3, repeats=3, default=(64, 4)):
     result, timings = {}, {}
     for cls, classes in (("sweep", SWEEP_CLASSES), ("update", UPDATE_CLASSES)):
         times = {}
-        for tile in _ordered(default):
+        for tile in _ordered(cls):
             sim.set_tiles(cls, *tile)
             P.copy_(P0)
             times[tile] = time_classes(sim, P, dt, classes, steps, repeats)
@@ -193,18 +195,18 @@ def tune_sim(sim, P, steps=3, repeats=3, default=(64, 4)):
     return result, timings
 
 
-def search(measure, default=(64, 4), repeats=3):
+def search(measure, repeats=3):
     """Coordinate search over the two tile classes with a caller's timer.
 
     measure(tiles) -> seconds (or ms) of some fixed work run with
     tiles = {"sweep": (tx, ty), "update": (tx, ty)}. The sweep tile is chosen
-    with the update tile at the default, then the update tile with the chosen
+    with the update tile at its default, then the update tile with the chosen
     sweep tile. Returns (tiles, {cls: best median})."""
-    tiles = {"sweep": default, "update": default}
+    tiles = dict(DEFAULT)
     best_t = {}
     for cls in ("sweep", "update"):
         times = {}
-        for tile in _ordered(default):
+        for tile in _ordered(cls):
             trial = dict(tiles, **{cls: tile})
             times[tile] = [measure(trial) for _ in range(repeats)]
         tiles[cls], best_t[cls] = pick(times)

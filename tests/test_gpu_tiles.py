@@ -9,7 +9,8 @@ import problems
 
 pytestmark = pytest.mark.gpu
 
-TILES = [(64, 4), (32, 2), (16, 4), (128, 2), (256, 1), (64, 1), (128, 1), (32, 8)]
+SWEEP_TILES = [(64, 8), (32, 2), (16, 4), (128, 2), (256, 1), (64, 1), (128, 4), (32, 16)]
+UPDATE_TILES = [(64, 4), (32, 8), (128, 1), (64, 1), (256, 1), (128, 2), (16, 4), (32, 2)]
 
 
 def evolve(lib, prm, P0, nsteps, sweep=None, update=None):
@@ -35,7 +36,7 @@ def evolve(lib, prm, P0, nsteps, sweep=None, update=None):
 def test_any_tile_gives_the_same_bits(lib, make):
     prm, P0 = make()
     ref, dt_ref = evolve(lib, prm, P0, 3)
-    for st, ut in zip(TILES[1:], TILES[::-1]):
+    for st, ut in zip(SWEEP_TILES[1:], UPDATE_TILES[1:]):
         out, dt = evolve(lib, prm, P0, 3, sweep=st, update=ut)
         assert dt == dt_ref, (st, ut)
         assert np.array_equal(out, ref), (st, ut)
@@ -44,16 +45,20 @@ def test_any_tile_gives_the_same_bits(lib, make):
 def test_tile_validation(lib):
     prm, _ = problems.linear_modes(n=8)
     sim = lib.Sim(prm)
-    assert sim.get_tiles("sweep") == (64, 4)
+    assert sim.get_tiles("sweep") == (64, 8)
     assert sim.get_tiles("update") == (64, 4)
-    for bad in [(48, 4), (64, 5), (512, 1), (8, 8), (16, 3), (0, 4), (64, 0)]:
+    for bad in [(48, 4), (32, 3), (512, 1), (8, 8), (16, 3), (0, 4), (64, 0), (64, 16)]:
         with pytest.raises(lib.GrmhdError):
             sim.set_tiles("sweep", *bad)
+    for bad in [(64, 8), (128, 4), (32, 16)]:                  # above the update's 256 threads
+        with pytest.raises(lib.GrmhdError):
+            sim.set_tiles("update", *bad)
     with pytest.raises(lib.GrmhdError):
         sim.set_tiles(7, 64, 4)
     sim.set_tiles("update", 128, 2)
+    sim.set_tiles("sweep", 128, 4)
     assert sim.get_tiles("update") == (128, 2)
-    assert sim.get_tiles("sweep") == (64, 4)
+    assert sim.get_tiles("sweep") == (128, 4)
     sim.close()
 
 
@@ -61,7 +66,7 @@ def test_batch_uses_its_first_jobs_tiles(lib):
     jobs = [problems.fm_torus(n1=48, n2=28, n3=4), problems.linear_modes(n=12, n3=9, kvec=(1, 1, 0))]
     refs = [evolve(lib, prm, P0, 2)[0] for prm, P0 in jobs]
     sims = [lib.Sim(prm) for prm, _ in jobs]
-    sims[0].set_tiles("sweep", 128, 2)
+    sims[0].set_tiles("sweep", 128, 4)
     sims[0].set_tiles("update", 32, 2)
     states = [s.to_device(P0) for s, (_, P0) in zip(sims, jobs)]
     dt0 = [s.get_dt(P) for s, P in zip(sims, states)]

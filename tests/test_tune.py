@@ -10,14 +10,16 @@ import problems
 from paper_2110_10191_amd import tune
 
 
-def test_candidates_are_legal_and_cover_the_default():
-    c = tune.candidates()
-    assert (64, 4) in c
+@pytest.mark.parametrize("cls,maxt", [("sweep", 512), ("update", 256)])
+def test_candidates_are_legal_and_cover_the_default(cls, maxt):
+    c = tune.candidates(cls)
+    assert tune.DEFAULT[cls] in c
     assert len(c) == len(set(c))
     for tx, ty in c:
         assert tx & (tx - 1) == 0 and 16 <= tx <= 256
-        assert (tx * ty) % 64 == 0 and tx * ty <= 256
+        assert (tx * ty) % 64 == 0 and tx * ty <= maxt
     assert {(256, 1), (128, 2), (64, 1), (32, 8)} <= set(c)
+    assert ((64, 8) in c) == (cls == "sweep")
 
 
 def test_bucket_separates_recon_precision_and_size():
@@ -49,6 +51,8 @@ def test_cache_ignores_illegal_or_corrupt_entries(tmp_path):
     path = tmp_path / "tiles.json"
     path.write_text(json.dumps({"d|h": {"k": {"sweep": [48, 4], "update": [64, 4]}}}))
     assert tune.TileCache(str(path), device="d", lib_hash="h").get("k") is None
+    path.write_text(json.dumps({"d|h": {"k": {"sweep": [64, 8], "update": [64, 8]}}}))   # 512 > update bound
+    assert tune.TileCache(str(path), device="d", lib_hash="h").get("k") is None
     path.write_text("{not json")
     c = tune.TileCache(str(path), device="d", lib_hash="h")
     assert c.get("k") is None
@@ -77,7 +81,7 @@ def test_tuning_returns_a_candidate_and_caches_it(lib, tmp_path):
     prm, P0 = problems.fm_torus(n1=64, n2=32, n3=16)
     cache = tune.TileCache(str(tmp_path / "tiles.json"))
     tiles = tune.tune_problem(prm, P0, cache=cache, steps=1, repeats=1)
-    assert tiles["sweep"] in tune.candidates() and tiles["update"] in tune.candidates()
+    assert tiles["sweep"] in tune.candidates("sweep") and tiles["update"] in tune.candidates("update")
     assert cache.get(tune.bucket(prm)) == tiles
     sim = lib.Sim(prm)
     assert tune.apply(sim, cache) == tiles
@@ -99,6 +103,6 @@ def test_search_finds_the_separable_minimum():
     tiles, best = tune.search(measure, repeats=2)
     assert tiles == {"sweep": (128, 2), "update": (32, 8)}
     assert best == {"sweep": 3.0, "update": 1.5}
-    assert len(calls) == 2 * 2 * len(tune.candidates())
-    # the default is tried first in each class
-    assert calls[0] == {"sweep": (64, 4), "update": (64, 4)}
+    assert len(calls) == 2 * (len(tune.candidates("sweep")) + len(tune.candidates("update")))
+    # the defaults are tried first
+    assert calls[0] == {"sweep": (64, 8), "update": (64, 4)}
