@@ -11,9 +11,9 @@ LLF fluxes, Flux-CT, predictor-corrector, FP64. Synthetic initial data from
 
 A step is one full predictor-corrector cycle of every zone, including the
 Courant step for the next one (dt <- min(dt_next, 1.3 dt)). By default the
-steps go through the batch calls with this one job, so the step size stays on
-the device and the host does not wait between steps (``--path host`` instead
-calls grmhd_step once a step and reads dt back each time). The metric is
+steps go through grmhd_run, which keeps the step size on the device so the
+host does not wait between steps (``--path host`` calls grmhd_step once a
+step and reads dt back each time; the two give identical states). The metric is
 zone-cycles per second: interior zones x steps / wall seconds over the timed
 steps (bracketed by device synchronisation). Kernel durations over the same
 timed region come from HIP events the library records on its stream around
@@ -214,9 +214,9 @@ def main():
     ap.add_argument("--workload", choices=["torus", "many"], default="torus",
                     help="torus: one large torus (default); many: 64 uneven jobs batched vs looped")
     ap.add_argument("--tune", action="store_true", help="autotune the batch tiles (workload many)")
-    ap.add_argument("--path", choices=["device", "host"], default="host",
-                    help="host: one grmhd_step per step with dt read back each step (default); device: "
-                         "steps through the batch calls with the step size kept on the device")
+    ap.add_argument("--path", choices=["device", "host"], default="device",
+                    help="device: grmhd_run, the step size kept on the device (default); host: one "
+                         "grmhd_step per step with dt read back each step")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="also run one plain device copy of this size (for counter scaling)")
     args = ap.parse_args()
@@ -268,28 +268,20 @@ def main():
         for name in g.KERNELS:
             kernels[name] = g.grmhd_profile_read(sim.ctx, name)
     else:
-        # the same kernels through the batch calls with one job: the step size
-        # stays on the device (dt <- min(dt_next, 1.3 dt) by a kernel), so the
-        # host never waits between steps; every launch is bracketed by events
-        b = g.Batch([sim])
-        b.set_dt([dt])
-        b.step([P], nsteps=args.warmup)
-        dts, _ = b.get()
-        print(f"[bench] warmup done, dt = {dts[0]:.3e}", file=sys.stderr, flush=True)
-        b.profile(True)
+        # grmhd_run: the same kernels with the step size kept on the device
+        # (dt <- min(dt_next, 1.3 dt) by a one-thread kernel), so the host
+        # never waits between steps; every launch is bracketed by events
+        dt = sim.run(P, args.warmup, dt)
+        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
+        g.grmhd_profile(sim.ctx, True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b.step([P], nsteps=args.steps)
-        dts, status = b.get()
+        dt = sim.run(P, args.steps, dt)
         torch.cuda.synchronize()
         secs = time.perf_counter() - t0
+        g.grmhd_profile(sim.ctx, False)
         for name in g.KERNELS:
-            kernels[name] = b.profile_read(name)
-        b.profile(False)
-        b.close()
-        dt = dts[0]
-        if status[0]:
-            print("[bench] non-finite signal speed in the timed steps", file=sys.stderr, flush=True)
+            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
     fails = sim.step_failures()
     divb = sim.divb(P)
     zones = n1 * n2 * n3

@@ -141,6 +141,16 @@ GRMHD_API int grmhd_get_dt(grmhd_ctx *ctx, double *P, double *dt);
  * a non-finite signal speed appeared (only checked when dt_next is given). */
 GRMHD_API int grmhd_step(grmhd_ctx *ctx, double *P, double dt, double *dt_next);
 
+/* nsteps predictor-corrector steps in place on P with the step size kept on
+ * the device: step n+1 uses min(cfl / sum_d (ctop_d / dx_d), 1.3 dt_n) from
+ * step n's corrector speeds, the same rule, evaluated in the same order, as a
+ * host loop of dt <- min(dt_next, 1.3 dt) around grmhd_step, so the results
+ * are identical; the host does not wait between steps. dt (host, in/out): the
+ * first step's size on entry, the size for the step after the last on exit.
+ * Synchronises once at the end. Returns GRMHD_ESTATE if a non-finite signal
+ * speed appeared (dt then stops growing). */
+GRMHD_API int grmhd_run(grmhd_ctx *ctx, double *P, int32_t nsteps, double *dt);
+
 /* max |div B| over cell corners, with div B the corner-centred divergence of
  * sqrt(-g) B (the quantity Flux-CT keeps at round-off, Implementation Notes).
  * Corners on non-periodic boundaries are excluded. Reads interior zones only.

@@ -14,7 +14,7 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 # every symbol include/grmhd.h declares
 EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
-    "grmhd_get_dt", "grmhd_step", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
+    "grmhd_get_dt", "grmhd_step", "grmhd_run", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
@@ -79,6 +79,7 @@ def _load():
         "grmhd_cons_to_prim": ([vp, vp, vp, vp, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_get_dt": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step": ([vp, vp, ctypes.c_double, dp], ctypes.c_int),
+        "grmhd_run": ([vp, vp, i32, dp], ctypes.c_int),
         "grmhd_divb": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step_failures": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -183,6 +184,13 @@ def grmhd_step(ctx, P, dt, want_dt_next=True):
     dn = ctypes.c_double()
     _check(lib.grmhd_step(ctx, _ptr(P), float(dt), ctypes.byref(dn) if want_dt_next else None), ctx)
     return dn.value if want_dt_next else None
+
+
+def grmhd_run(ctx, P, nsteps, dt):
+    """nsteps steps with the step size kept on the device; returns the next dt."""
+    d = ctypes.c_double(float(dt))
+    _check(lib.grmhd_run(ctx, _ptr(P), int(nsteps), ctypes.byref(d)), ctx)
+    return d.value
 
 
 def grmhd_divb(ctx, P):
@@ -382,6 +390,9 @@ class Sim:
 
     def step(self, P, dt, want_dt_next=True):
         return grmhd_step(self.ctx, P, dt, want_dt_next)
+
+    def run(self, P, nsteps, dt):
+        return grmhd_run(self.ctx, P, nsteps, dt)
 
     def divb(self, P):
         return grmhd_divb(self.ctx, P)

@@ -117,7 +117,9 @@ hipError_t dalloc(T** ptr, size_t bytes) {
 
 
 // predictor or corrector substep; dsrc is the base state (source of Dirichlet ghosts)
-int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop) {
+// dt_dev: when not null the step is dt_scale * *dt_dev (read on the device)
+int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop,
+            const double* dt_dev = nullptr, double dt_scale = 1.0) {
   hipStream_t s = c->stream;
   {
     ProfScope ps(c->prof, s, GRMHD_K_GHOSTS);
@@ -133,7 +135,7 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
   {
     ProfScope ps(c->prof, s, GRMHD_K_UPDATE);
     HIP_OR_FAIL(c, launch_update(c->mixed, c->d, c->t, c->up, c->F[0], c->F[1], c->F[2], Pb, Ps, Pout,
-                                 c->flags, dt, c->ctr, s),
+                                 c->flags, dt, dt_dev, dt_scale, c->ctr, s),
                 "update");
   }
   {
@@ -396,6 +398,38 @@ int grmhd_step(grmhd_ctx* ctx, double* P, double dt, double* dt_next) {
   st = substep(ctx, ctx->Ph, P, P, dt, true);
   if (st != GRMHD_OK) return st;
   if (dt_next) return read_dt(ctx, dt_next);
+  return GRMHD_OK;
+}
+
+int grmhd_run(grmhd_ctx* ctx, double* P, int32_t nsteps, double* dt) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !dt) return fail(ctx, GRMHD_EINVAL, "run: NULL argument");
+  if (nsteps < 0) return fail(ctx, GRMHD_EINVAL, "run: nsteps < 0");
+  if (!(*dt > 0.0) || !std::isfinite(*dt)) return fail(ctx, GRMHD_EINVAL, "run: dt must be finite and > 0");
+  struct {
+    double dt;
+    int status;
+  } host{*dt, 0};
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&ctx->ctr->dt, &host.dt, sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+              "set dt");
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&ctx->ctr->status, &host.status, sizeof(int), hipMemcpyHostToDevice, ctx->stream),
+              "set status");
+  const double* dtp = &ctx->ctr->dt;
+  for (int s = 0; s < nsteps; ++s) {
+    HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 8, ctx->stream), "reset");
+    int st = substep(ctx, P, P, ctx->Ph, 0.0, false, dtp, 0.5);
+    if (st != GRMHD_OK) return st;
+    st = substep(ctx, ctx->Ph, P, P, 0.0, true, dtp, 1.0);
+    if (st != GRMHD_OK) return st;
+    HIP_OR_FAIL(ctx, launch_ctx_dt(ctx->ctr, ctx->p.cfl, ctx->dx[0], ctx->dx[1], ctx->dx[2], ctx->stream), "dt");
+  }
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.dt, &ctx->ctr->dt, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+              "read dt");
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.status, &ctx->ctr->status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+              "read status");
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+  *dt = host.dt;
+  if (host.status) return fail(ctx, GRMHD_ESTATE, "non-finite signal speed in the state");
   return GRMHD_OK;
 }
 

@@ -188,26 +188,37 @@ __global__ void reset_batch_kernel(BatchView bv, int mask) {
   reset_counters(bv.jobs[jb].ctr, mask);
 }
 
-// dt <- min(cfl / sum_d (ctop_d / dx_d), 1.3 dt); a non-finite speed keeps dt
-// and raises the job's status flag
+// dt <- min(cfl / sum_d (ctop_d / dx_d), 1.3 dt) (1.3 dt when every speed is
+// 0); a non-finite speed keeps dt and raises the status flag. The same
+// operations, in the same order, as the host rule after grmhd_step.
+__device__ void device_dt(const unsigned long long* ctop, const double* dx, double cfl, double* dt, int* status) {
+  double sum = 0.0;
+  bool finite = true;
+  for (int d = 0; d < 3; ++d) {
+    const double c = __longlong_as_double((long long)ctop[d]);
+    finite = finite && isfinite(c);
+    sum += c / dx[d];
+  }
+  if (!finite) {
+    *status = 1;
+    return;
+  }
+  const double dn = sum > 0.0 ? cfl / sum : __builtin_inf();
+  *dt = fmin(dn, 1.3 * *dt);
+}
+
+__global__ void dt_ctx_kernel(Counters* ctr, double cfl, double dx1, double dx2, double dx3) {
+  if (threadIdx.x != 0) return;
+  const double dx[3] = {dx1, dx2, dx3};
+  device_dt(ctr->ctop, dx, cfl, &ctr->dt, &ctr->status);
+}
+
 __global__ void dt_batch_kernel(BatchView bv) {
   const int jb = (int)(blockIdx.x * blockDim.x + threadIdx.x);
   if (jb >= bv.njobs) return;
   const JobDesc& J = bv.jobs[jb];
-  double sum = 0.0;
-  bool finite = true;
   const double dx[3] = {J.up.dx1, J.up.dx2, J.up.dx3};
-  for (int d = 0; d < 3; ++d) {
-    const double c = __longlong_as_double((long long)J.ctr->ctop[d]);
-    finite = finite && isfinite(c);
-    sum += c / dx[d];
-  }
-  if (!finite || !(sum > 0.0)) {
-    if (!finite) *J.status = 1;
-    return;
-  }
-  const double dn = J.p.cfl / sum;
-  *J.dt = fmin(dn, 1.3 * *J.dt);
+  device_dt(J.ctr->ctop, dx, J.p.cfl, J.dt, J.status);
 }
 
 }  // namespace
@@ -228,6 +239,11 @@ hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, c
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr, 2);
   hipLaunchKernelGGL(divb_kernel, dim3((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.n3), dim3(64, 4, 1), 0, s, p,
                      d, t.cent, P, &ctr->divb);
+  return hipGetLastError();
+}
+
+hipError_t launch_ctx_dt(Counters* ctr, double cfl, double dx1, double dx2, double dx3, hipStream_t s) {
+  hipLaunchKernelGGL(dt_ctx_kernel, dim3(1), dim3(64), 0, s, ctr, cfl, dx1, dx2, dx3);
   return hipGetLastError();
 }
 

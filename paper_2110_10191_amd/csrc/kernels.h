@@ -21,6 +21,8 @@ struct Counters {
   unsigned long long divb;     // max |div B| (double bits)
   unsigned int fail;           // failed inversions of the current substep
   unsigned int fail_total;     // failed inversions since the last reset
+  double dt;                   // step size kept on the device (grmhd_run)
+  int status;                  // 1 once a non-finite speed met the device dt rule
 };
 
 // physical constants the update kernels need
@@ -98,10 +100,14 @@ hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Table
 hipError_t launch_sweep(int dir, int recon, bool mixed, const Dims& d, const Tables& t, double gam,
                         const double* P, void* F, unsigned long long* ctop, hipStream_t s);
 
+// the step is dt, or dt_scale * *dt_dev when dt_dev is not null
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up,
                          const void* F1, const void* F2, const void* F3, const double* Pb,
                          const double* Ps, double* Pout, int8_t* flags, double dt,
-                         Counters* ctr, hipStream_t s);
+                         const double* dt_dev, double dt_scale, Counters* ctr, hipStream_t s);
+
+// ctr->dt <- min(cfl / sum_d(ctop_d / dx_d), 1.3 ctr->dt) on the device
+hipError_t launch_ctx_dt(Counters* ctr, double cfl, double dx1, double dx2, double dx3, hipStream_t s);
 
 hipError_t launch_fixup(const Dims& d, const Tables& t, const UpdateParams& up, double* P,
                         const int8_t* flags, const Counters* ctr, hipStream_t s);

@@ -254,12 +254,15 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
 // Left free the compiler takes 224 (two waves) and the kernel waits on its
 // loads and long dependency chains with too little to switch to; the FP64
 // variant fits 168 without spilling.
-template <typename TF>
+template <typename TF, bool DEV_DT>
 __global__ __launch_bounds__(256, 3) void update_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
                                                      const TF* __restrict__ F1, const TF* __restrict__ F2,
                                                      const TF* __restrict__ F3, const double* Pb,
                                                      const double* __restrict__ Ps, double* Pout,
-                                                     int8_t* __restrict__ flags, double dt, Counters* ctr) {
+                                                     int8_t* __restrict__ flags, double dt,
+                                                     const double* __restrict__ dt_dev, double dt_scale,
+                                                     Counters* ctr) {
+  if (DEV_DT) dt = dt_scale * *dt_dev;
   update_body<TF>(d, cent, up, F1, F2, F3, Pb, Ps, Pout, flags, dt, ctr, (int)blockIdx.x);
 }
 
@@ -371,15 +374,27 @@ __global__ __launch_bounds__(256) void u2p_kernel(Dims d, const double* __restri
 
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up, const void* F1,
                          const void* F2, const void* F3, const double* Pb, const double* Ps, double* Pout,
-                         int8_t* flags, double dt, Counters* ctr, hipStream_t s) {
+                         int8_t* flags, double dt, const double* dt_dev, double dt_scale, Counters* ctr,
+                         hipStream_t s) {
   const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
   dim3 blk(d.utx, d.uty, 1), grd(nblk);
-  if (mixed)
-    hipLaunchKernelGGL(update_kernel<float>, grd, blk, 0, s, d, t.cent, up, (const float*)F1, (const float*)F2,
-                       (const float*)F3, Pb, Ps, Pout, flags, dt, ctr);
-  else
-    hipLaunchKernelGGL(update_kernel<double>, grd, blk, 0, s, d, t.cent, up, (const double*)F1,
-                       (const double*)F2, (const double*)F3, Pb, Ps, Pout, flags, dt, ctr);
+  if (mixed) {
+    const float *f1 = (const float*)F1, *f2 = (const float*)F2, *f3 = (const float*)F3;
+    if (dt_dev)
+      hipLaunchKernelGGL((update_kernel<float, true>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+                         flags, dt, dt_dev, dt_scale, ctr);
+    else
+      hipLaunchKernelGGL((update_kernel<float, false>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+                         flags, dt, dt_dev, dt_scale, ctr);
+  } else {
+    const double *f1 = (const double*)F1, *f2 = (const double*)F2, *f3 = (const double*)F3;
+    if (dt_dev)
+      hipLaunchKernelGGL((update_kernel<double, true>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+                         flags, dt, dt_dev, dt_scale, ctr);
+    else
+      hipLaunchKernelGGL((update_kernel<double, false>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+                         flags, dt, dt_dev, dt_scale, ctr);
+  }
   return hipGetLastError();
 }
 

@@ -296,3 +296,29 @@ def test_context_bytes_matches_the_device_allocation(lib):
     assert used <= cb + 12 * (2 << 20)          # 12 allocations, up to 2 MiB rounding each
     n1p = -(-(96 + 6) // 8) * 8
     assert sb == 8 * 8 * (32 + 6) * (64 + 6) * n1p
+
+
+def test_run_keeps_dt_on_device_and_equals_the_host_loop(lib):
+    """grmhd_run applies dt <- min(dt_next, 1.3 dt) on the device: the same
+    step sizes and the same bits as the host loop around grmhd_step."""
+    for make in (lambda: problems.fm_torus(n1=48, n2=28, n3=4),
+                 lambda: problems.fm_torus(n1=40, n2=18, n3=3, recon=problems.RECON_WENO5,
+                                           precision=problems.MIXED)):
+        prm, P0 = make()
+        a = lib.Sim(prm)
+        Pa = a.to_device(P0)
+        dt0 = a.get_dt(Pa)
+        dt = dt0
+        for _ in range(5):
+            dt = min(a.step(Pa, dt), 1.3 * dt)
+        b = lib.Sim(prm)
+        Pb = b.to_device(P0)
+        dt_b = b.run(Pb, 2, dt0)
+        dt_b = b.run(Pb, 3, dt_b)
+        assert dt_b == dt
+        assert np.array_equal(a.to_host(Pa), b.to_host(Pb))
+        assert b.run(Pb, 0, dt_b) == dt_b
+        with pytest.raises(lib.GrmhdError):
+            b.run(Pb, 1, -1.0)
+        a.close()
+        b.close()
