@@ -49,7 +49,7 @@ __host__ __device__ inline int cell_of(const Dims& d, int k, int j, int i) {
 }
 __host__ __device__ inline int tab_of(const Dims& d, int j, int i) { return (j + NG) * d.s2 + (i + NG); }
 
-// Loads and stores as (wave-uniform base pointer) + (32-bit unsigned byte offset):
+// Loads as (wave-uniform base pointer) + (32-bit unsigned byte offset):
 // the backend can then keep the base in scalar registers and share one 32-bit
 // vector offset across all components, instead of a 64-bit vector address per
 // load. Every array here is < 4 GiB per component (checked at init).
@@ -57,33 +57,6 @@ template <typename S>
 __device__ inline S ldu(const S* base, unsigned byte_off) {
   return *(const S*)((const char*)base + byte_off);
 }
-template <typename S>
-__device__ inline void stu(S* base, unsigned byte_off, S v) {
-  *(S*)((char*)base + byte_off) = v;
-}
-
-// Buffer-resource loads: the descriptor (base, size) sits in scalar registers,
-// the per-lane 32-bit byte offset is shared by every load of a thread, and the
-// component / neighbour offset goes into the scalar offset operand. Reads
-// beyond the descriptor's size return 0 instead of touching memory.
-constexpr int BUF_DWORD3 = 0x00020000;  // raw (untyped) buffer on CDNA
-
-struct Buf {
-  __amdgpu_buffer_rsrc_t r;
-};
-
-__device__ inline Buf make_buf(const void* base, unsigned bytes) {
-  Buf b;
-  b.r = __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, BUF_DWORD3);
-  return b;
-}
-__device__ inline double bld(const Buf& b, unsigned voff, int soff_bytes, double) {
-  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, soff_bytes, 0));
-}
-__device__ inline float bld(const Buf& b, unsigned voff, int soff_bytes, float) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, soff_bytes, 0));
-}
-
 template <typename T>
 struct Geo {
   T gcov[10];
@@ -91,19 +64,6 @@ struct Geo {
   T gdet;
   T alpha;
 };
-
-// geometry from a table behind a buffer descriptor: component c at byte
-// offset c * ts * sizeof(S) (scalar) + point * sizeof(S) (vector)
-template <typename T, typename S>
-__device__ inline void load_geo_buf(Geo<T>& g, const Buf& tab, int ts, unsigned pt_bytes) {
-  const int cs = ts * (int)sizeof(S);
-#pragma unroll
-  for (int c = 0; c < 10; ++c) g.gcov[c] = (T)bld(tab, pt_bytes, (T_GCOV + c) * cs, S());
-#pragma unroll
-  for (int c = 0; c < 10; ++c) g.gcon[c] = (T)bld(tab, pt_bytes, (T_GCON + c) * cs, S());
-  g.gdet = (T)bld(tab, pt_bytes, T_GDET * cs, S());
-  g.alpha = (T)bld(tab, pt_bytes, T_ALPHA * cs, S());
-}
 
 // component c of a table lives at tab + c * ts; off is the 2D point index
 template <typename T, typename S>
