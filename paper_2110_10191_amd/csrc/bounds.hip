@@ -133,10 +133,11 @@ __global__ __launch_bounds__(256) void ghost_batch_kernel(BatchView bv, int corr
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
   const int b = (int)blockIdx.x - offs[jb];
-  double* tgt = corrector ? J.Ph : J.P;
-  if (DIR == 1) ghost_x1_body(J.p, J.d, J.t.cent, tgt, J.P, b * (int)blockDim.x + (int)threadIdx.x);
-  else if (DIR == 2) ghost_x2_body(J.p, J.d, tgt, J.P, b);
-  else ghost_x3_body(J.p, J.d, tgt, J.P, b);
+  double* tgt = global_ptr(corrector ? J.Ph : J.P);
+  const double* src = global_ptr(J.P);
+  if (DIR == 1) ghost_x1_body(J.p, J.d, global_ptr(J.t.cent), tgt, src, b * (int)blockDim.x + (int)threadIdx.x);
+  else if (DIR == 2) ghost_x2_body(J.p, J.d, tgt, src, b);
+  else ghost_x3_body(J.p, J.d, tgt, src, b);
 }
 
 // corner-centred divergence of sqrt(-g) B; corner (i, j, k) sits at (i-1/2, j-1/2, k-1/2)

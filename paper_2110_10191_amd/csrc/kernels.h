@@ -63,6 +63,17 @@ struct BatchView {
   int stx, sty, utx, uty;  // block tiles shared by every job of the batch
 };
 
+// A pointer read from the device job table is a generic pointer to the
+// compiler, which then emits flat loads (slower, and counted against both the
+// vector and the scalar memory counters). Every array here is device global
+// memory: say so, so the loads stay global loads.
+// (Through an integer: a direct generic -> global -> generic cast pair is
+// folded away and the information lost.)
+template <typename T>
+__device__ inline T* global_ptr(T* p) {
+  return (T*)(__attribute__((address_space(1))) T*)(uintptr_t)p;
+}
+
 __device__ inline int batch_job(const int* offs, int njobs, int b) {
   int lo = 0, hi = njobs;
   while (hi - lo > 1) {

@@ -110,8 +110,9 @@ __global__ __launch_bounds__(512) void sweep_batch_kernel(BatchView bv, int corr
   const int* offs = bv.offs + (PH_SWEEP1 + D - 1) * (bv.njobs + 1);
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
-  sweep_body<D, RECON, T>(J.d, corrector ? J.Ph : J.P, face_table<T>(J.t, D), (T*)J.F[D - 1], (T)J.p.gam,
-                          (int)blockIdx.x - offs[jb], want_ctop ? J.ctr->ctop : nullptr);
+  sweep_body<D, RECON, T>(J.d, global_ptr(corrector ? J.Ph : J.P), global_ptr(face_table<T>(J.t, D)),
+                          global_ptr((T*)J.F[D - 1]), (T)J.p.gam, (int)blockIdx.x - offs[jb],
+                          want_ctop ? global_ptr(J.ctr->ctop) : nullptr);
 }
 
 template <int D, int RECON, typename T>

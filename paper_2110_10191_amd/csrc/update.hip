@@ -273,8 +273,10 @@ __global__ __launch_bounds__(256, 3) void update_batch_kernel(BatchView bv, int 
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
   const double dt = corrector ? *J.dt : 0.5 * *J.dt;
-  update_body<TF>(J.d, J.t.cent, J.up, (const TF*)J.F[0], (const TF*)J.F[1], (const TF*)J.F[2], J.P,
-                  corrector ? J.Ph : J.P, corrector ? J.P : J.Ph, J.flags, dt, J.ctr, (int)blockIdx.x - offs[jb]);
+  update_body<TF>(J.d, global_ptr(J.t.cent), J.up, global_ptr((const TF*)J.F[0]), global_ptr((const TF*)J.F[1]),
+                  global_ptr((const TF*)J.F[2]), global_ptr(J.P), global_ptr(corrector ? J.Ph : J.P),
+                  global_ptr(corrector ? J.P : J.Ph), global_ptr(J.flags), dt, global_ptr(J.ctr),
+                  (int)blockIdx.x - offs[jb]);
 }
 
 // failed zone <- mean of the hydro primitives of its non-failed interior
@@ -325,7 +327,8 @@ __global__ __launch_bounds__(256) void fixup_batch_kernel(BatchView bv, int corr
   const int* offs = bv.offs + PH_UPDATE * (bv.njobs + 1);
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
-  fixup_body(J.d, J.t.cent, J.up, corrector ? J.P : J.Ph, J.flags, J.ctr, (int)blockIdx.x - offs[jb]);
+  fixup_body(J.d, global_ptr(J.t.cent), J.up, global_ptr(corrector ? J.P : J.Ph), global_ptr(J.flags),
+             global_ptr(J.ctr), (int)blockIdx.x - offs[jb]);
 }
 
 __global__ __launch_bounds__(256) void p2u_kernel(Dims d, const double* __restrict__ cent, double gam,
