@@ -69,6 +69,27 @@ def algorithmic_bytes(kernel, prm, mixed):
     raise KeyError(kernel)
 
 
+def device_copy_bandwidth(torch, dev, gib=1.0, reps=5):
+    """Best of a few plain device-to-device copies, bytes read + written per second."""
+    nel = int(gib * 2 ** 30) // 8
+    a = torch.ones(nel, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / 1e3
+        best = t if best is None else min(best, t)
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nel * 8 / best
+
+
 def measured_traffic(kernel, workload):
     """HBM bytes per launch of ``kernel`` from the committed counter summary
     (profiles/hbm_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a plain
@@ -306,6 +327,22 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+
+    # the other two views of the HBM roofline: the whole step's compulsory
+    # state traffic (read P^n, write P_h; read P^n and P_h, write P^{n+1}:
+    # 320 B a zone, plus the 2D geometry once per step) at the measured rate,
+    # and the dominant kernel's measured HBM bytes over its time; both against
+    # the nominal peak and against a plain device copy measured here
+    copy_bw = device_copy_bandwidth(torch, dev)
+    step_bytes = 320.0 * zones + 2 * 150 * 8 * n1 * n2
+    views = {"copy_GBps": copy_bw / 1e9,
+             "step_compulsory_bytes_per_zone_cycle": step_bytes / zones,
+             "step_compulsory_frac": value * step_bytes / zones / HBM_PEAK,
+             "step_compulsory_frac_of_copy": value * step_bytes / zones / copy_bw}
+    if roofline["traffic"]:
+        views["measured_frac"] = roofline["traffic"] / (ms / n / 1e3) / HBM_PEAK
+        views["measured_frac_of_copy"] = roofline["traffic"] / (ms / n / 1e3) / copy_bw
+    roofline["views"] = views
 
     out = {
         "metric": "zone-cycles/s per GPU + % HBM roofline; batched-serving p50/p99 job latency",
