@@ -157,11 +157,12 @@ GRMHD_API int grmhd_run(grmhd_ctx *ctx, double *P, int32_t nsteps, double *dt);
  * max_divb (host) is written; synchronises. */
 GRMHD_API int grmhd_divb(grmhd_ctx *ctx, const double *P, double *max_divb);
 
-/* Failed-inversion count of the last grmhd_step (both substeps); synchronises. */
+/* Failed-inversion count of the last step taken by grmhd_step or grmhd_run
+ * (both substeps); synchronises. */
 GRMHD_API int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
 
 /* Kernel timing for measurement. grmhd_profile(ctx, 1) clears the record and
- * starts bracketing every kernel launch of grmhd_step with HIP events on the
+ * starts bracketing every kernel launch of grmhd_step and grmhd_run with HIP events on the
  * context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
  * one kernel class, the summed device time in ms and the launch count since
  * the last clear; synchronises. Timing adds two event records per launch. */

@@ -142,7 +142,7 @@ struct FluxView {
   __device__ TF raw(int v, int c) const { return F[v * sv + c]; }
 };
 
-// b: block index within this job's grid (64 x 4 tiles, XCD-aware order)
+// b: block index within this job's grid (the update tile d.utx x d.uty, XCD-aware order)
 template <typename TF, bool EARLY_PS = false>
 __device__ void update_body(const Dims& d, const double* __restrict__ cent, const UpdateParams& up,
                             const TF* __restrict__ F1p, const TF* __restrict__ F2p, const TF* __restrict__ F3p,
