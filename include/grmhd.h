@@ -151,6 +151,27 @@ GRMHD_API int grmhd_step(grmhd_ctx *ctx, double *P, double dt, double *dt_next);
  * speed appeared (dt then stops growing). */
 GRMHD_API int grmhd_run(grmhd_ctx *ctx, double *P, int32_t nsteps, double *dt);
 
+/* The pieces of a step, for drivers that own the ghost zones of some
+ * boundaries themselves (a domain split over several contexts exchanging
+ * halos). grmhd_step(ctx, P, dt) is: fill_ghosts(P, P); substep(P, P, P_h,
+ * dt/2, 0); fill_ghosts(P_h, P); substep(P_h, P, P, dt, 1).
+ *
+ * grmhd_fill_ghosts: the ghost zones of P from the problem's boundary
+ * conditions, x1 then x2 then x3; DIRICHLET ghosts are copied from base (NULL:
+ * P's own are kept). Asynchronous.
+ * grmhd_substep: one predictor or corrector substep without the ghost fill:
+ * P_out = bounds(invert(U(P_b) + dt L(P_s))) then the fixup, with L from P_s's
+ * face fluxes (its ghost zones must be valid) and the geometric source at P_s.
+ * P_out may be P_b. want_speeds != 0 records the per-direction maximum signal
+ * speeds of this substep's faces with an interior transverse index.
+ * Asynchronous.
+ * grmhd_speeds: those three maxima (ctop_1, ctop_2, ctop_3), host array;
+ * synchronises; GRMHD_ESTATE if one is not finite. */
+GRMHD_API int grmhd_fill_ghosts(grmhd_ctx *ctx, double *P, const double *base);
+GRMHD_API int grmhd_substep(grmhd_ctx *ctx, const double *Ps, const double *Pb, double *Pout, double dt,
+                            int32_t want_speeds);
+GRMHD_API int grmhd_speeds(grmhd_ctx *ctx, double ctop[3]);
+
 /* max |div B| over cell corners, with div B the corner-centred divergence of
  * sqrt(-g) B (the quantity Flux-CT keeps at round-off, Implementation Notes).
  * Corners on non-periodic boundaries are excluded. Reads interior zones only.

@@ -14,7 +14,7 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 # every symbol include/grmhd.h declares
 EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
-    "grmhd_get_dt", "grmhd_step", "grmhd_run", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
+    "grmhd_get_dt", "grmhd_step", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_speeds", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
@@ -80,6 +80,9 @@ def _load():
         "grmhd_get_dt": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step": ([vp, vp, ctypes.c_double, dp], ctypes.c_int),
         "grmhd_run": ([vp, vp, i32, dp], ctypes.c_int),
+        "grmhd_fill_ghosts": ([vp, vp, vp], ctypes.c_int),
+        "grmhd_substep": ([vp, vp, vp, vp, ctypes.c_double, i32], ctypes.c_int),
+        "grmhd_speeds": ([vp, dp], ctypes.c_int),
         "grmhd_divb": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step_failures": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -191,6 +194,20 @@ def grmhd_run(ctx, P, nsteps, dt):
     d = ctypes.c_double(float(dt))
     _check(lib.grmhd_run(ctx, _ptr(P), int(nsteps), ctypes.byref(d)), ctx)
     return d.value
+
+
+def grmhd_fill_ghosts(ctx, P, base=None):
+    _check(lib.grmhd_fill_ghosts(ctx, _ptr(P), _ptr(base)), ctx)
+
+
+def grmhd_substep(ctx, Ps, Pb, Pout, dt, want_speeds=False):
+    _check(lib.grmhd_substep(ctx, _ptr(Ps), _ptr(Pb), _ptr(Pout), float(dt), 1 if want_speeds else 0), ctx)
+
+
+def grmhd_speeds(ctx):
+    v = (ctypes.c_double * 3)()
+    _check(lib.grmhd_speeds(ctx, v), ctx)
+    return tuple(v)
 
 
 def grmhd_divb(ctx, P):

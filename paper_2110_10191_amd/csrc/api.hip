@@ -116,12 +116,13 @@ hipError_t dalloc(T** ptr, size_t bytes) {
 }
 
 
-// predictor or corrector substep; dsrc is the base state (source of Dirichlet ghosts)
-// dt_dev: when not null the step is dt_scale * *dt_dev (read on the device)
+// predictor or corrector substep; Pb is the base state (also the source of
+// Dirichlet ghosts). dt_dev: when not null the step is dt_scale * *dt_dev (read
+// on the device). fill = false leaves the ghost zones of Ps as they are.
 int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop,
-            const double* dt_dev = nullptr, double dt_scale = 1.0) {
+            const double* dt_dev = nullptr, double dt_scale = 1.0, bool fill = true) {
   hipStream_t s = c->stream;
-  {
+  if (fill) {
     ProfScope ps(c->prof, s, GRMHD_K_GHOSTS);
     HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s), "ghost fill");
   }
@@ -145,17 +146,22 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
   return GRMHD_OK;
 }
 
-int read_dt(grmhd_ctx* c, double* dt) {
+int read_speeds(grmhd_ctx* c, double v[3]) {
   unsigned long long bits[3];
   HIP_OR_FAIL(c, hipMemcpyAsync(bits, c->ctr->ctop, sizeof(bits), hipMemcpyDeviceToHost, c->stream), "copy ctop");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "synchronize");
+  for (int d = 0; d < 3; ++d) std::memcpy(&v[d], &bits[d], sizeof(double));
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(v[d])) return fail(c, GRMHD_ESTATE, "non-finite signal speed in the state");
+  return GRMHD_OK;
+}
+
+int read_dt(grmhd_ctx* c, double* dt) {
+  double v[3];
+  const int st = read_speeds(c, v);
+  if (st != GRMHD_OK) return st;
   double sum = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    double v;
-    std::memcpy(&v, &bits[d], sizeof(v));
-    if (!std::isfinite(v)) return fail(c, GRMHD_ESTATE, "non-finite signal speed in the state");
-    sum += v / c->dx[d];
-  }
+  for (int d = 0; d < 3; ++d) sum += v[d] / c->dx[d];
   *dt = sum > 0.0 ? c->p.cfl / sum : INFINITY;
   return GRMHD_OK;
 }
@@ -431,6 +437,26 @@ int grmhd_run(grmhd_ctx* ctx, double* P, int32_t nsteps, double* dt) {
   *dt = host.dt;
   if (host.status) return fail(ctx, GRMHD_ESTATE, "non-finite signal speed in the state");
   return GRMHD_OK;
+}
+
+int grmhd_fill_ghosts(grmhd_ctx* ctx, double* P, const double* base) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P) return fail(ctx, GRMHD_EINVAL, "fill_ghosts: NULL state");
+  HIP_OR_FAIL(ctx, launch_fill_ghosts(ctx->p, ctx->d, ctx->t, P, base ? base : P, ctx->stream), "ghost fill");
+  return GRMHD_OK;
+}
+
+int grmhd_substep(grmhd_ctx* ctx, const double* Ps, const double* Pb, double* Pout, double dt, int32_t want_speeds) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!Ps || !Pb || !Pout) return fail(ctx, GRMHD_EINVAL, "substep: NULL state");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GRMHD_EINVAL, "substep: dt must be finite and > 0");
+  return substep(ctx, const_cast<double*>(Ps), const_cast<double*>(Pb), Pout, dt, want_speeds != 0, nullptr, 1.0,
+                 false);
+}
+
+int grmhd_speeds(grmhd_ctx* ctx, double ctop[3]) {
+  if (!ctx || !ctop) return GRMHD_EINVAL;
+  return read_speeds(ctx, ctop);
 }
 
 int grmhd_step_failures(grmhd_ctx* ctx, int64_t* n_fail) {
