@@ -17,6 +17,11 @@ Layout: primitives are float64 arrays ``[8, n3+6, n2+6, n1+6]`` (three ghost
 layers per side, x1 fastest) in the order rho, u, u~1, u~2, u~3, B1, B2, B3.
 Geometry is axisymmetric: 2D tables ``[..., n2+6, n1+6]`` broadcast over x3.
 
+Electron heating (``oracle.electrons``): two advected entropies per zone and
+the partition of the dissipated heat by a heating model; readings E1-E6 are
+stated in that module, whose model formulas are parity unpinned beyond their
+published limits.
+
 Parity status per function (pins live in ``tests/test_oracle_*.py``):
 every function is pinned to a closed form, an invariant or a brute-force
 check, except the floor ordering and the fixup average, whose definitions are

@@ -307,12 +307,14 @@ def fixup(P, failed):
 
 # ----------------------------------------------------------------------------- substep / step
 
-def substep(Ps, Pb, grid, dt):
+def substep(Ps, Pb, grid, dt, mass_flux=False):
     """One substep on a padded block.
 
     Ps: flux-state primitives with ghosts filled (padded block); Pb: base-state
     primitives on the block interior. Returns (P_new interior, failed mask,
-    ctop maxima per direction over the interior faces).
+    ctop maxima per direction over the interior faces), and with
+    ``mass_flux`` also the three mass-flux arrays (component 0 of the face
+    fluxes after Flux-CT, padded grid).
     """
     prm = grid.prm
     gam = prm["gam"]
@@ -344,6 +346,8 @@ def substep(Ps, Pb, grid, dt):
             floors(Pn, geo, grid.r[J, I], prm, mask=failed)
     cmax = (np.nanmax(C1[K, J, NG:NG + n1 + 1]), np.nanmax(C2[K, NG:NG + n2 + 1, I]),
             np.nanmax(C3[NG:NG + nk + 1, J, I]))
+    if mass_flux:
+        return Pn, failed, cmax, (F1[0], F2[0], F3[0])
     return Pn, failed, cmax
 
 
