@@ -69,6 +69,7 @@ enum { GRMHD_OPT_FLOORS = 1, GRMHD_OPT_FIXUP = 2 };
 
 #define GRMHD_NG 3
 #define GRMHD_NVAR 8
+#define GRMHD_NSCALAR 2
 
 /* One problem. Code coordinates:
  *   MINKOWSKI_CART: Cartesian, metric diag(-1, 1, 1, 1);
@@ -172,6 +173,40 @@ GRMHD_API int grmhd_substep(grmhd_ctx *ctx, const double *Ps, const double *Pb, 
                             int32_t want_speeds);
 GRMHD_API int grmhd_speeds(grmhd_ctx *ctx, double ctop[3]);
 
+/* ---- Electron heating (Implementation Notes: iharm3D tracks the dissipation
+ * and splits it between ions and electrons after Ressler et al. 2015, with the
+ * heating models of Howes 2010, Kawazura et al. 2019, Werner et al. 2018 and
+ * Rowan et al. 2017; with electron temperatures evolved, the bounds also keep
+ * P_gas / rho^gamma below 3).
+ *
+ * E: caller-owned float64 device array [2][n3 + 6][n2 + 6][n1p], the state
+ * layout with two variables (same strides as a state): the total entropy
+ * K_tot = P_gas / rho^gam and the electron entropy K_e = P_e / rho^(4/3).
+ *
+ * grmhd_step_electrons: one predictor-corrector step as grmhd_step, in place
+ * on P and E, in which every substep also
+ *   - advects both entropies with the mass flux: sqrt(-g) rho u^t K is updated
+ *     conservatively with face fluxes F_mass K*, K* the face value from the
+ *     problem's reconstruction on the upwind side of F_mass;
+ *   - after the other bounds and the fixup, lowers u to 3 rho^gam / (gam - 1)
+ *     where it is above;
+ *   - sets K_tot to the entropy of the new state and gives the electrons the
+ *     fraction f_e of the heat the difference implies:
+ *     K_e = K_e,adv + f_e (1/3)/(gam - 1) rho^(gam - 4/3) (K_tot - K_tot,adv),
+ *     held within [0, rho^(gam - 4/3) K_tot] (0 <= P_e <= P_gas).
+ * model: GRMHD_HEAT_CONSTANT (f_e = fel, 0 <= fel <= 1) or one of the four
+ * models (fel ignored). The ghost zones of E follow the primitives' rules
+ * without the axis sign change and the inflow fix. The first call on a context
+ * allocates 4 doubles per padded zone of scratch, held until grmhd_free.
+ * dt_next and the errors as grmhd_step; EINVAL also for an unknown model or
+ * fel outside [0, 1]. */
+enum {
+  GRMHD_HEAT_CONSTANT = 0, GRMHD_HEAT_KAWAZURA = 1, GRMHD_HEAT_WERNER = 2, GRMHD_HEAT_ROWAN = 3,
+  GRMHD_HEAT_HOWES = 4
+};
+GRMHD_API int grmhd_step_electrons(grmhd_ctx *ctx, double *P, double *E, double dt, int32_t model, double fel,
+                                   double *dt_next);
+
 /* max |div B| over cell corners, with div B the corner-centred divergence of
  * sqrt(-g) B (the quantity Flux-CT keeps at round-off, Implementation Notes).
  * Corners on non-periodic boundaries are excluded. Reads interior zones only.
@@ -183,13 +218,14 @@ GRMHD_API int grmhd_divb(grmhd_ctx *ctx, const double *P, double *max_divb);
 GRMHD_API int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
 
 /* Kernel timing for measurement. grmhd_profile(ctx, 1) clears the record and
- * starts bracketing every kernel launch of grmhd_step and grmhd_run with HIP events on the
+ * starts bracketing every kernel launch of grmhd_step, grmhd_step_electrons
+ * (GRMHD_K_ELECTRONS: the scalar ghosts, advection and heating) and grmhd_run with HIP events on the
  * context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
  * one kernel class, the summed device time in ms and the launch count since
  * the last clear; synchronises. Timing adds two event records per launch. */
 enum {
   GRMHD_K_GHOSTS = 0, GRMHD_K_SWEEP1 = 1, GRMHD_K_SWEEP2 = 2, GRMHD_K_SWEEP3 = 3,
-  GRMHD_K_UPDATE = 4, GRMHD_K_FIXUP = 5, GRMHD_K_COUNT = 6
+  GRMHD_K_UPDATE = 4, GRMHD_K_FIXUP = 5, GRMHD_K_ELECTRONS = 6, GRMHD_K_COUNT = 7
 };
 GRMHD_API int grmhd_profile(grmhd_ctx *ctx, int32_t enable);
 GRMHD_API int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);

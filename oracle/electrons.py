@@ -213,12 +213,3 @@ def step(P, E, grid, dt, model=MODEL_CONSTANT, fel=0.5):
     En[it] = En_i
     return Pn, En, dt_from_ctop(cmax, grid)
 
-
-def initial_scalars(P, gam, te_ti=1.0):
-    """E from primitives: K_tot from u, K_e for electrons at T_e/T_i = te_ti
-    (P_e = P_gas te_ti / (1 + te_ti))."""
-    rho = np.where(P[0] > 0, P[0], 1.0)
-    pg = (gam - 1.0) * P[1]
-    ktot = pg / rho ** gam
-    kel = pg * te_ti / (1.0 + te_ti) / rho ** GAM_E
-    return np.array([ktot, kel])

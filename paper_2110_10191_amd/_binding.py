@@ -14,12 +14,14 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 # every symbol include/grmhd.h declares
 EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
-    "grmhd_get_dt", "grmhd_step", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_speeds", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
+    "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_speeds", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
 ]
-KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5}
+KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5, "electrons": 6}
+NSCALAR = 2
+HEAT_MODELS = {"constant": 0, "kawazura": 1, "werner": 2, "rowan": 3, "howes": 4}
 TILES = {"sweep": 0, "update": 1}
 
 
@@ -79,6 +81,7 @@ def _load():
         "grmhd_cons_to_prim": ([vp, vp, vp, vp, i32, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_get_dt": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step": ([vp, vp, ctypes.c_double, dp], ctypes.c_int),
+        "grmhd_step_electrons": ([vp, vp, vp, ctypes.c_double, i32, ctypes.c_double, dp], ctypes.c_int),
         "grmhd_run": ([vp, vp, i32, dp], ctypes.c_int),
         "grmhd_fill_ghosts": ([vp, vp, vp], ctypes.c_int),
         "grmhd_substep": ([vp, vp, vp, vp, ctypes.c_double, i32], ctypes.c_int),
@@ -186,6 +189,15 @@ def grmhd_get_dt(ctx, P):
 def grmhd_step(ctx, P, dt, want_dt_next=True):
     dn = ctypes.c_double()
     _check(lib.grmhd_step(ctx, _ptr(P), float(dt), ctypes.byref(dn) if want_dt_next else None), ctx)
+    return dn.value if want_dt_next else None
+
+
+def grmhd_step_electrons(ctx, P, E, dt, model=0, fel=0.5, want_dt_next=True):
+    """One step of P and the electron entropies E; model: a HEAT_MODELS name or value."""
+    m = HEAT_MODELS[model] if isinstance(model, str) else int(model)
+    dn = ctypes.c_double()
+    _check(lib.grmhd_step_electrons(ctx, _ptr(P), _ptr(E), float(dt), m, float(fel),
+                                    ctypes.byref(dn) if want_dt_next else None), ctx)
     return dn.value if want_dt_next else None
 
 
@@ -380,9 +392,14 @@ class Sim:
     def empty_state(self):
         return self.torch.zeros(self.shape, dtype=self.torch.float64, device=self.device)
 
+    def empty_scalars(self):
+        """Device array of the two electron-heating entropies (state strides)."""
+        return self.torch.zeros((NSCALAR,) + tuple(self.shape[1:]), dtype=self.torch.float64, device=self.device)
+
     def to_device(self, P):
-        """[8, n3+6, n2+6, n1+6] numpy -> padded device tensor."""
-        t = self.empty_state()
+        """[nvar, n3+6, n2+6, n1+6] numpy -> padded device tensor (8 primitives
+        or the 2 electron entropies)."""
+        t = self.empty_state() if P.shape[0] == NVAR else self.empty_scalars()
         n1 = P.shape[-1]
         t[..., :n1] = self.torch.from_numpy(P).to(self.device)
         return t
@@ -410,6 +427,9 @@ class Sim:
 
     def run(self, P, nsteps, dt):
         return grmhd_run(self.ctx, P, nsteps, dt)
+
+    def step_electrons(self, P, E, dt, model=0, fel=0.5, want_dt_next=True):
+        return grmhd_step_electrons(self.ctx, P, E, dt, model, fel, want_dt_next)
 
     def divb(self, P):
         return grmhd_divb(self.ctx, P)

@@ -27,7 +27,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
     "-I", INCLUDE, "-I", CSRC,
 ]
-SOURCES = ["geometry.hip", "bounds.hip", "sweep.hip", "update.hip", "api.hip", "batch.hip"]
+SOURCES = ["geometry.hip", "bounds.hip", "sweep.hip", "update.hip", "electrons.hip", "api.hip", "batch.hip"]
 
 
 def hipcc():

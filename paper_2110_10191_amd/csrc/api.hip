@@ -105,7 +105,7 @@ Dims make_dims(const grmhd_problem& p) {
 
 void free_all(grmhd_ctx* c) {
   void* ptrs[] = {c->t.cent, c->t.f1, c->t.f2, c->t.centf, c->t.f1f, c->t.f2f,
-                  c->Ph, c->F[0], c->F[1], c->F[2], c->flags, c->ctr};
+                  c->Ph, c->F[0], c->F[1], c->F[2], c->flags, c->ctr, c->Eh, c->Uk};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
 }
@@ -116,15 +116,31 @@ hipError_t dalloc(T** ptr, size_t bytes) {
 }
 
 
+// the electron entropies of a substep: flux state Es (ghosts refilled here),
+// base state Eb (also the source of Dirichlet ghosts), result Eout
+struct ElectronPass {
+  double* Es;
+  const double* Eb;
+  double* Eout;
+  int model;
+  double fel;
+};
+
 // predictor or corrector substep; Pb is the base state (also the source of
 // Dirichlet ghosts). dt_dev: when not null the step is dt_scale * *dt_dev (read
 // on the device). fill = false leaves the ghost zones of Ps as they are.
+// el: also advect and heat the electron entropies (host dt only).
 int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop,
-            const double* dt_dev = nullptr, double dt_scale = 1.0, bool fill = true) {
+            const double* dt_dev = nullptr, double dt_scale = 1.0, bool fill = true,
+            const ElectronPass* el = nullptr) {
   hipStream_t s = c->stream;
   if (fill) {
     ProfScope ps(c->prof, s, GRMHD_K_GHOSTS);
     HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s), "ghost fill");
+  }
+  if (el) {
+    ProfScope ps(c->prof, s, GRMHD_K_ELECTRONS);
+    HIP_OR_FAIL(c, launch_fill_scalar_ghosts(c->p, c->d, el->Es, el->Eb, s), "scalar ghost fill");
   }
   HIP_OR_FAIL(c, launch_reset(c->ctr, want_ctop ? (1 | 4) : 4, s), "reset");
   for (int dir = 1; dir <= 3; ++dir) {
@@ -132,6 +148,13 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
     HIP_OR_FAIL(c, launch_sweep(dir, c->p.recon, c->mixed, c->d, c->t, c->p.gam, Ps, c->F[dir - 1],
                                 want_ctop ? c->ctr->ctop : nullptr, s),
                 "sweep");
+  }
+  if (el) {
+    // before the update: in the corrector it overwrites the base state in place
+    ProfScope ps(c->prof, s, GRMHD_K_ELECTRONS);
+    HIP_OR_FAIL(c, launch_scalar_advect(c->mixed, c->p.recon, c->d, c->t, c->up, c->F[0], c->F[1], c->F[2], Pb,
+                                        el->Eb, el->Es, c->Uk, dt, s),
+                "scalar advection");
   }
   {
     ProfScope ps(c->prof, s, GRMHD_K_UPDATE);
@@ -142,6 +165,11 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
   {
     ProfScope ps(c->prof, s, GRMHD_K_FIXUP);
     HIP_OR_FAIL(c, launch_fixup(c->d, c->t, c->up, Pout, c->flags, c->ctr, s), "fixup");
+  }
+  if (el) {
+    ProfScope ps(c->prof, s, GRMHD_K_ELECTRONS);
+    HIP_OR_FAIL(c, launch_electron_heat(c->d, c->t, c->p.gam, Pout, c->Uk, el->Eout, el->model, el->fel, s),
+                "electron heating");
   }
   return GRMHD_OK;
 }
@@ -402,6 +430,37 @@ int grmhd_step(grmhd_ctx* ctx, double* P, double dt, double* dt_next) {
   int st = substep(ctx, P, P, ctx->Ph, 0.5 * dt, false);
   if (st != GRMHD_OK) return st;
   st = substep(ctx, ctx->Ph, P, P, dt, true);
+  if (st != GRMHD_OK) return st;
+  if (dt_next) return read_dt(ctx, dt_next);
+  return GRMHD_OK;
+}
+
+int grmhd_step_electrons(grmhd_ctx* ctx, double* P, double* E, double dt, int32_t model, double fel,
+                         double* dt_next) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !E) return fail(ctx, GRMHD_EINVAL, "step_electrons: NULL state");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GRMHD_EINVAL, "step_electrons: dt must be finite and > 0");
+  if (model < GRMHD_HEAT_CONSTANT || model > GRMHD_HEAT_HOWES)
+    return fail(ctx, GRMHD_EINVAL, "step_electrons: unknown heating model");
+  if (model == GRMHD_HEAT_CONSTANT && !(fel >= 0.0 && fel <= 1.0))
+    return fail(ctx, GRMHD_EINVAL, "step_electrons: fel must lie in [0, 1]");
+  if (!ctx->Eh) {
+    const size_t bytes = (size_t)GRMHD_NSCALAR * ctx->d.sv * sizeof(double);
+    if (dalloc(&ctx->Eh, bytes) != hipSuccess || dalloc(&ctx->Uk, bytes) != hipSuccess) {
+      if (ctx->Eh) (void)hipFree(ctx->Eh);
+      if (ctx->Uk) (void)hipFree(ctx->Uk);
+      ctx->Eh = ctx->Uk = nullptr;
+      return fail(ctx, GRMHD_ENOMEM, "step_electrons: scratch allocation failed");
+    }
+    // ghost and padding zones of the half-step entropies that no rule writes stay finite
+    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->Eh, 0, bytes, ctx->stream), "clear scratch");
+  }
+  HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 8, ctx->stream), "reset");
+  const ElectronPass pred{E, E, ctx->Eh, model, fel};
+  int st = substep(ctx, P, P, ctx->Ph, 0.5 * dt, false, nullptr, 1.0, true, &pred);
+  if (st != GRMHD_OK) return st;
+  const ElectronPass corr{ctx->Eh, E, E, model, fel};
+  st = substep(ctx, ctx->Ph, P, P, dt, true, nullptr, 1.0, true, &corr);
   if (st != GRMHD_OK) return st;
   if (dt_next) return read_dt(ctx, dt_next);
   return GRMHD_OK;

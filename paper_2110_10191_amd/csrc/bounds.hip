@@ -1,7 +1,8 @@
 // Ghost zones, the div B monitor, counter resets and the per-job time step.
 //
 // Ghost fill (three ghost layers), in the order x1 (interior j, k), x2 (all i,
-// interior k), x3 (all i, j) so corners are consistent:
+// interior k), x3 (all i, j) so corners are consistent (the electron-heating
+// scalars follow the same rules without the inflow fix and the axis sign change):
 //   periodic  - wrap;
 //   outflow   - copy the nearest interior zone; where the copied radial
 //               four-velocity points into the domain, u~1 is reset so u^1 = 0;
@@ -40,8 +41,11 @@ __device__ void inflow_fix(double* P, int stride, int c0, const double* cent, in
   P[2 * stride + c0] = c * root;
 }
 
-// ---- bodies: idx / b are thread / block indices within one job's grid
+// ---- bodies: idx / b are thread / block indices within one job's grid.
+// NVAR variables of stride d.sv; SCALAR: advected scalars (no inflow fix, no
+// sign change on the axis), otherwise the primitives.
 
+template <int NVAR = NV, bool SCALAR = false>
 __device__ void ghost_x1_body(const grmhd_problem& p, const Dims& d, const double* cent, double* P,
                               const double* dsrc, int idx) {
   if (idx >= 2 * NG * d.n2 * d.n3) return;
@@ -55,17 +59,18 @@ __device__ void ghost_x1_body(const grmhd_problem& p, const Dims& d, const doubl
   const int cg = cell_of(d, k, j, g);
   if (type == GRMHD_BC_DIRICHLET) {
     if (dsrc != P)
-      for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+      for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
     return;
   }
   const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n1) : (side == 0 ? 0 : d.n1 - 1);
   const int cs = cell_of(d, k, j, src);
-  for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
-  if (type == GRMHD_BC_OUTFLOW) inflow_fix(P, d.sv, cg, cent, d.ts, tab_of(d, j, g), side);
+  for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
+  if (!SCALAR && type == GRMHD_BC_OUTFLOW) inflow_fix(P, d.sv, cg, cent, d.ts, tab_of(d, j, g), side);
 }
 
 __device__ inline int ghost_tiles(const Dims& d) { return (d.n1 + 2 * NG + GB - 1) / GB; }
 
+template <int NVAR = NV, bool SCALAR = false>
 __device__ void ghost_x2_body(const grmhd_problem& p, const Dims& d, double* P, const double* dsrc, int b) {
   const int tiles = ghost_tiles(d);
   const int bx = b % tiles, rest = b / tiles;
@@ -78,7 +83,7 @@ __device__ void ghost_x2_body(const grmhd_problem& p, const Dims& d, double* P, 
   const int cg = cell_of(d, k, g, i);
   if (type == GRMHD_BC_DIRICHLET) {
     if (dsrc != P)
-      for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+      for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
     return;
   }
   int src;
@@ -86,12 +91,13 @@ __device__ void ghost_x2_body(const grmhd_problem& p, const Dims& d, double* P, 
   else if (type == GRMHD_BC_POLAR) src = side == 0 ? m : d.n2 - 1 - m;
   else src = side == 0 ? 0 : d.n2 - 1;
   const int cs = cell_of(d, k, src, i);
-  for (int v = 0; v < NV; ++v) {
+  for (int v = 0; v < NVAR; ++v) {
     const double q = P[v * d.sv + cs];
-    P[v * d.sv + cg] = (type == GRMHD_BC_POLAR && (v == 3 || v == 6)) ? -q : q;
+    P[v * d.sv + cg] = (!SCALAR && type == GRMHD_BC_POLAR && (v == 3 || v == 6)) ? -q : q;
   }
 }
 
+template <int NVAR = NV, bool SCALAR = false>
 __device__ void ghost_x3_body(const grmhd_problem& p, const Dims& d, double* P, const double* dsrc, int b) {
   const int tiles = ghost_tiles(d);
   const int bx = b % tiles, rest = b / tiles;
@@ -104,12 +110,12 @@ __device__ void ghost_x3_body(const grmhd_problem& p, const Dims& d, double* P, 
   const int cg = cell_of(d, g, j, i);
   if (type == GRMHD_BC_DIRICHLET) {
     if (dsrc != P)
-      for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+      for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
     return;
   }
   const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n3) : (side == 0 ? 0 : d.n3 - 1);
   const int cs = cell_of(d, src, j, i);
-  for (int v = 0; v < NV; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
+  for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
 }
 
 // ---- single-job kernels
@@ -123,6 +129,17 @@ __global__ __launch_bounds__(GB) void ghost_x2_kernel(grmhd_problem p, Dims d, d
 }
 __global__ __launch_bounds__(GB) void ghost_x3_kernel(grmhd_problem p, Dims d, double* P, const double* dsrc) {
   ghost_x3_body(p, d, P, dsrc, (int)blockIdx.x);
+}
+
+// the two advected entropies of the electron-heating step
+__global__ __launch_bounds__(256) void scalar_ghost_x1_kernel(grmhd_problem p, Dims d, double* E, const double* dsrc) {
+  ghost_x1_body<GRMHD_NSCALAR, true>(p, d, nullptr, E, dsrc, (int)(blockIdx.x * blockDim.x + threadIdx.x));
+}
+__global__ __launch_bounds__(GB) void scalar_ghost_x2_kernel(grmhd_problem p, Dims d, double* E, const double* dsrc) {
+  ghost_x2_body<GRMHD_NSCALAR, true>(p, d, E, dsrc, (int)blockIdx.x);
+}
+__global__ __launch_bounds__(GB) void scalar_ghost_x3_kernel(grmhd_problem p, Dims d, double* E, const double* dsrc) {
+  ghost_x3_body<GRMHD_NSCALAR, true>(p, d, E, dsrc, (int)blockIdx.x);
 }
 
 // ---- batched kernels: the block finds its job, then runs the same body
@@ -232,6 +249,17 @@ hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Table
   const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
   hipLaunchKernelGGL(ghost_x2_kernel, dim3(tiles * 2 * NG * d.n3), dim3(GB, 1, 1), 0, s, p, d, P, dsrc);
   hipLaunchKernelGGL(ghost_x3_kernel, dim3(tiles * (d.n2 + 2 * NG) * 2 * NG), dim3(GB, 1, 1), 0, s, p, d, P, dsrc);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_scalar_ghosts(const grmhd_problem& p, const Dims& d, double* E, const double* dsrc,
+                                     hipStream_t s) {
+  const int n1threads = 2 * NG * d.n2 * d.n3;
+  hipLaunchKernelGGL(scalar_ghost_x1_kernel, dim3((n1threads + 255) / 256), dim3(256, 1, 1), 0, s, p, d, E, dsrc);
+  const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
+  hipLaunchKernelGGL(scalar_ghost_x2_kernel, dim3(tiles * 2 * NG * d.n3), dim3(GB, 1, 1), 0, s, p, d, E, dsrc);
+  hipLaunchKernelGGL(scalar_ghost_x3_kernel, dim3(tiles * (d.n2 + 2 * NG) * 2 * NG), dim3(GB, 1, 1), 0, s, p, d, E,
+                     dsrc);
   return hipGetLastError();
 }
 

@@ -91,6 +91,8 @@ struct grmhd_ctx {
   bool mixed;
   Tables t;
   double* Ph;
+  double* Eh;  // electron heating scratch (allocated on first use): half-step entropies
+  double* Uk;  // and the advected sqrt(-g) rho u^t K of the current substep
   void* F[3];
   int8_t* flags;
   Counters* ctr;

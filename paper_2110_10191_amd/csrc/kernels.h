@@ -133,5 +133,17 @@ hipError_t launch_cons_to_prim(const Dims& d, const Tables& t, const UpdateParam
 hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P,
                        Counters* ctr, hipStream_t s);
 
+// electron heating: the ghost zones of the two entropies (the primitives'
+// rules without the axis sign change and the inflow fix); the advection of
+// U_K = sqrt(-g) rho u^t K from the face mass fluxes (F of double or float);
+// the u ceiling and the heating of the new state
+hipError_t launch_fill_scalar_ghosts(const grmhd_problem& p, const Dims& d, double* E, const double* dirichlet_src,
+                                     hipStream_t s);
+hipError_t launch_scalar_advect(bool mixed, int recon, const Dims& d, const Tables& t, const UpdateParams& up,
+                                const void* F1, const void* F2, const void* F3, const double* Pb, const double* Eb,
+                                const double* Es, double* Uk, double dt, hipStream_t s);
+hipError_t launch_electron_heat(const Dims& d, const Tables& t, double gam, double* P, const double* Uk, double* E,
+                                int model, double fel, hipStream_t s);
+
 // zero the counters selected by mask (1: ctop, 2: divb, 4: fail, 8: fail_total)
 hipError_t launch_reset(Counters* ctr, int mask, hipStream_t s);

@@ -26,10 +26,11 @@ from .params import (NG, MINKOWSKI_CART, KERR_MKS, KERR_FMKS, RECON_MC, RECON_WE
 from .modes import linear_modes, mode_solution
 from .torus import fm_torus
 from .bondi import bondi
+from .electrons import electron_scalars
 
 __all__ = [
     "NG", "MINKOWSKI_CART", "KERR_MKS", "KERR_FMKS", "RECON_MC", "RECON_WENO5",
     "FP64", "MIXED", "BC_PERIODIC", "BC_OUTFLOW", "BC_POLAR", "BC_DIRICHLET",
     "base_problem", "kerr_grid_extent", "padded_shape",
-    "linear_modes", "mode_solution", "fm_torus", "bondi",
+    "linear_modes", "mode_solution", "fm_torus", "bondi", "electron_scalars",
 ]

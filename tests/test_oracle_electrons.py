@@ -67,7 +67,7 @@ def _uniform_flow(n, v1=0.5):
     P = np.zeros(problems.params.padded_shape(prm))
     P[0], P[1], P[2] = 1.0, 0.1, v1
     x = (np.arange(n) + 0.5) / n
-    E = el.initial_scalars(P, prm["gam"])
+    E = problems.electron_scalars(P, prm["gam"])
     E[1, :, :, NG:NG + n] = 0.03 * (1.0 + 0.5 * np.sin(2.0 * np.pi * x))
     return prm, P, E, x
 
@@ -96,7 +96,7 @@ def test_uniform_scalar_stays_uniform_in_a_magnetised_flow():
     # E4 is inactive here and the primitives are the plain step's
     prm, P = problems.linear_modes(n=12, n3=4, amp=1e-3)
     it = _interior(prm)
-    E = el.initial_scalars(P, prm["gam"])
+    E = problems.electron_scalars(P, prm["gam"])
     E[1] = 0.25 * np.min(E[1][it[1:]])
     g = oracle.Grid(prm)
     dt = oracle.get_dt(P, g)
@@ -134,7 +134,7 @@ def test_scale_invariance(model):
     out = []
     for s in (1.0, lam):
         prm, P = _sod(n, s)
-        E = el.initial_scalars(P, prm["gam"], te_ti=0.5)
+        E = problems.electron_scalars(P, prm["gam"], te_ti=0.5)
         P1, E1 = _evolve(prm, P, E, 12, dt=0.25 / n, model=model, fel=0.5)
         it = _interior(prm)
         out.append((P1[it], E1[it], E[it]))
@@ -154,7 +154,7 @@ def test_proportional_partition_is_kept_on_the_torus():
     prm, P = problems.fm_torus(n1=32, n2=16, n3=4, gam=4.0 / 3.0)
     te_ti = 0.5
     c = te_ti / (1.0 + te_ti)
-    E = el.initial_scalars(P, prm["gam"], te_ti=te_ti)
+    E = problems.electron_scalars(P, prm["gam"], te_ti=te_ti)
     P1, E1 = _evolve(prm, P, E, 3, model=el.MODEL_CONSTANT, fel=c)
     it = _interior(prm)
     np.testing.assert_allclose(E1[1][it[1:]], c * E1[0][it[1:]], rtol=1e-12)
@@ -165,7 +165,7 @@ def test_proportional_partition_is_kept_on_the_torus():
 def test_bounds_on_the_torus(model):
     prm, P = problems.fm_torus(n1=32, n2=16, n3=4)
     gam = prm["gam"]
-    E = el.initial_scalars(P, gam)
+    E = problems.electron_scalars(P, gam)
     P1, E1 = _evolve(prm, P, E, 2, model=model)
     it = _interior(prm)
     rho, u = P1[0][it[1:]], P1[1][it[1:]]
