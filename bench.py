@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--path", choices=["device", "host"], default="device",
                     help="device: grmhd_run, the step size kept on the device (default); host: one "
                          "grmhd_step per step with dt read back each step")
+    ap.add_argument("--electrons", choices=["constant", "kawazura", "werner", "rowan", "howes", "sharma"], default=None,
+                    help="step the electron entropies too (grmhd_step_electrons, host-driven dt) with "
+                         "this heating model (constant: f_e = 0.5)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="also run one plain device copy of this size (for counter scaling)")
     args = ap.parse_args()
@@ -272,7 +275,25 @@ def main():
 
     dt = sim.get_dt(P)
     kernels = {}
-    if args.path == "host":
+    if args.electrons:
+        # the fluid step plus the three electron passes per substep; one
+        # grmhd_step_electrons call per step, dt read back every step
+        E = sim.to_device(problems.electron_scalars(P0, prm["gam"]))
+        for _ in range(args.warmup):
+            dt = min(sim.step_electrons(P, E, dt, args.electrons), 1.3 * dt)
+        torch.cuda.synchronize()
+        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
+        g.grmhd_profile(sim.ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dt = min(sim.step_electrons(P, E, dt, args.electrons), 1.3 * dt)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        g.grmhd_profile(sim.ctx, False)
+        for name in g.KERNELS:
+            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
+    elif args.path == "host":
         # one grmhd_step call per step; dt read back to the host every step
         for _ in range(args.warmup):
             dt = min(sim.step(P, dt), 1.3 * dt)
@@ -315,6 +336,8 @@ def main():
     per_launch = algorithmic_bytes(dom, prm, mixed)
     achieved = per_launch / (ms / n / 1e3)
     workload = f"fm_torus_{n1}x{n2}x{n3}_{args.recon}_{args.precision}"
+    if args.electrons:
+        workload += f"_electrons_{args.electrons}"
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK, "traffic": measured_traffic(dom, workload),
                 "traffic_unit": "bytes per launch", "kernel": dom,
@@ -344,6 +367,19 @@ def main():
         views["measured_frac_of_copy"] = roofline["traffic"] / (ms / n / 1e3) / copy_bw
     roofline["views"] = views
 
+    if args.electrons:
+        # the electron passes of a step (scalar ghosts, advection, heating, two
+        # substeps each) against their own compulsory bytes: advection reads
+        # rho and u~ of the base state, both entropies of the base and the flux
+        # state and the three mass fluxes and writes U_K; heating reads the
+        # new primitives and U_K and writes both entropies
+        fb = 4 if mixed else 8
+        per_zone = 2 * ((4 + 2 + 2 + 2) * 8 + 3 * fb + (8 + 2 + 2) * 8)
+        e_ms = kernels["electrons"][0] / args.steps
+        roofline["electron_passes"] = {"ms_per_step": e_ms, "algorithmic_bytes_per_zone_cycle": per_zone,
+                                       "achieved_GBps": per_zone * zones / (e_ms / 1e3) / 1e9,
+                                       "frac": per_zone * zones / (e_ms / 1e3) / HBM_PEAK}
+
     out = {
         "metric": "zone-cycles/s per GPU + % HBM roofline; batched-serving p50/p99 job latency",
         "value": value,
@@ -360,7 +396,8 @@ def main():
         "config": {"workload": workload,
                    "grid": [n1, n2, n3], "a": prm["a"], "recon": args.recon,
                    "precision": args.precision, "coords": "fmks", "r_out": 1000.0,
-                   "driver": args.path},
+                   "driver": "host" if args.electrons else args.path,
+                   "electrons": args.electrons},
         "roofline": roofline,
         "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kernels.items()},
         "checks": {"max_divb": divb, "failed_inversions_last_step": fails, "dt": dt},

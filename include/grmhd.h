@@ -175,8 +175,8 @@ GRMHD_API int grmhd_speeds(grmhd_ctx *ctx, double ctop[3]);
 
 /* ---- Electron heating (Implementation Notes: iharm3D tracks the dissipation
  * and splits it between ions and electrons after Ressler et al. 2015, with the
- * heating models of Howes 2010, Kawazura et al. 2019, Werner et al. 2018 and
- * Rowan et al. 2017; with electron temperatures evolved, the bounds also keep
+ * heating models of Howes 2010, Kawazura et al. 2019, Werner et al. 2018,
+ * Rowan et al. 2017 and Sharma et al. 2007; with electron temperatures evolved, the bounds also keep
  * P_gas / rho^gamma below 3).
  *
  * E: caller-owned float64 device array [2][n3 + 6][n2 + 6][n1p], the state
@@ -194,7 +194,7 @@ GRMHD_API int grmhd_speeds(grmhd_ctx *ctx, double ctop[3]);
  *     fraction f_e of the heat the difference implies:
  *     K_e = K_e,adv + f_e (1/3)/(gam - 1) rho^(gam - 4/3) (K_tot - K_tot,adv),
  *     held within [0, rho^(gam - 4/3) K_tot] (0 <= P_e <= P_gas).
- * model: GRMHD_HEAT_CONSTANT (f_e = fel, 0 <= fel <= 1) or one of the four
+ * model: GRMHD_HEAT_CONSTANT (f_e = fel, 0 <= fel <= 1) or one of the five
  * models (fel ignored). The ghost zones of E follow the primitives' rules
  * without the axis sign change and the inflow fix. The first call on a context
  * allocates 4 doubles per padded zone of scratch, held until grmhd_free.
@@ -202,7 +202,7 @@ GRMHD_API int grmhd_speeds(grmhd_ctx *ctx, double ctop[3]);
  * fel outside [0, 1]. */
 enum {
   GRMHD_HEAT_CONSTANT = 0, GRMHD_HEAT_KAWAZURA = 1, GRMHD_HEAT_WERNER = 2, GRMHD_HEAT_ROWAN = 3,
-  GRMHD_HEAT_HOWES = 4
+  GRMHD_HEAT_HOWES = 4, GRMHD_HEAT_SHARMA = 5
 };
 GRMHD_API int grmhd_step_electrons(grmhd_ctx *ctx, double *P, double *E, double dt, int32_t model, double fel,
                                    double *dt_next);

@@ -38,15 +38,19 @@ E6  f_e: a constant, or one of four models as functions of beta_i = P_i /
                      Q_i/Q_e = 0.92 (c2^2 + beta_i^x)/(c3^2 + beta_i^x) sqrt(m_p theta / m_e) exp(-1/beta_i),
                      x = 2 - 0.2 log10 theta, c2 = 1.6/theta,
                      c3 = 18 + 5 log10 theta (theta > 1) or 18 (beta_i^x capped at e^700);
-    with f_e = 1/(1 + Q_i/Q_e) where a ratio is given. The Sharma et al. 2007
-    model is not built.
+      Sharma 2007:   Q_i/Q_e = sqrt(T_i/T_e) / 3 (the turbulent-heating ratio
+                     as commonly quoted from that work; no formula in the paper);
+    with f_e = 1/(1 + Q_i/Q_e) where a ratio is given.
 
-Parity status: E1-E5 are pinned by invariants (a uniform K_e/K_tot stays
-uniform under advection; an adiabatic smooth flow heats nothing to truncation
-order; the heat given to the electrons is f_e of the total; bounds hold). The
-model formulas of E6 are the cited papers' as read here: parity unpinned beyond
-their limits (f_e -> 1 as beta_i -> 0 for Kawazura and Howes; Werner between
-1/4 and 1/2; Rowan at most 1/2).
+Parity status: E1-E5 are pinned by properties of the equations (a passive
+scalar carried by a uniform flow converges to its exact translation at second
+order; a uniform scalar stays uniform; ideal MHD is scale free, which fixes the
+rho^(gamma - gamma_e) factor; electrons holding and receiving the same fraction
+of entropy and heat keep it; the bounds hold). The model formulas of E6 are the
+cited papers' as read here: parity unpinned beyond their published limits
+(f_e -> 1 as beta_i -> 0 for Kawazura and Howes, Q_i/Q_e -> 35 at high beta_i
+for Kawazura, Werner between 1/4 and 1/2, Rowan at most 1/2, Sharma 3/4 at
+T_e = T_i).
 """
 
 import numpy as np
@@ -60,7 +64,7 @@ from .step import (_interior, _geo2, fill_ghosts, substep, dt_from_ctop, AXIS, B
 GAM_E = 4.0 / 3.0
 KAPPA_MAX = 3.0
 MP_ME = 1836.15267343
-MODEL_CONSTANT, MODEL_KAWAZURA, MODEL_WERNER, MODEL_ROWAN, MODEL_HOWES = 0, 1, 2, 3, 4
+MODEL_CONSTANT, MODEL_KAWAZURA, MODEL_WERNER, MODEL_ROWAN, MODEL_HOWES, MODEL_SHARMA = 0, 1, 2, 3, 4, 5
 
 
 def fill_scalar_ghosts(E, grid):
@@ -151,6 +155,9 @@ def heating_fraction(model, fel, rho, u, kel, bsq, gam):
         x = 2.0 - 0.2 * lt
         bx = np.exp(np.minimum(x * np.log(beta), 700.0))   # beta^x, kept finite
         qi_qe = 0.92 * (c2 * c2 + bx) / (c3 * c3 + bx) * np.sqrt(MP_ME * theta) * np.exp(-1.0 / beta)
+        return 1.0 / (1.0 + qi_qe)
+    if model == MODEL_SHARMA:
+        qi_qe = np.sqrt(pi / np.maximum(pe, 1e-300)) / 3.0
         return 1.0 / (1.0 + qi_qe)
     raise ValueError(f"unknown heating model {model}")
 

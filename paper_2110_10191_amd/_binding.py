@@ -21,7 +21,7 @@ EXPORTED = [
 ]
 KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5, "electrons": 6}
 NSCALAR = 2
-HEAT_MODELS = {"constant": 0, "kawazura": 1, "werner": 2, "rowan": 3, "howes": 4}
+HEAT_MODELS = {"constant": 0, "kawazura": 1, "werner": 2, "rowan": 3, "howes": 4, "sharma": 5}
 TILES = {"sweep": 0, "update": 1}
 
 

@@ -440,7 +440,7 @@ int grmhd_step_electrons(grmhd_ctx* ctx, double* P, double* E, double dt, int32_
   if (!ctx) return GRMHD_EINVAL;
   if (!P || !E) return fail(ctx, GRMHD_EINVAL, "step_electrons: NULL state");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GRMHD_EINVAL, "step_electrons: dt must be finite and > 0");
-  if (model < GRMHD_HEAT_CONSTANT || model > GRMHD_HEAT_HOWES)
+  if (model < GRMHD_HEAT_CONSTANT || model > GRMHD_HEAT_SHARMA)
     return fail(ctx, GRMHD_EINVAL, "step_electrons: unknown heating model");
   if (model == GRMHD_HEAT_CONSTANT && !(fel >= 0.0 && fel <= 1.0))
     return fail(ctx, GRMHD_EINVAL, "step_electrons: fel must lie in [0, 1]");

@@ -1,7 +1,7 @@
 // Electron heating (Implementation Notes: the dissipation is tracked and split
 // between ions and electrons after Ressler et al. 2015, with the heating
-// models of Kawazura et al. 2019, Werner et al. 2018, Rowan et al. 2017 and
-// Howes 2010). Two passes per substep around the fluid update:
+// models of Kawazura et al. 2019, Werner et al. 2018, Rowan et al. 2017,
+// Howes 2010 and Sharma et al. 2007). Two passes per substep around the fluid update:
 //
 //   scalar advection (after the sweeps, before the fluid update overwrites the
 //   base state): for both entropies K (K_tot = P_gas / rho^gamma and
@@ -28,6 +28,7 @@
 //             sqrt(theta m_p/m_e) exp(-1/beta_i), x = 2 - 0.2 log10 theta,
 //             c2 = 1.6/theta, c3 = 18 + 5 log10 theta (theta > 1) else 18,
 //             beta_i^x capped at e^700;
+//   Sharma:   Q_i/Q_e = sqrt(T_i/T_e) / 3 (the ratio commonly quoted from that work);
 // with f_e = 1 / (1 + Q_i/Q_e) where a ratio is given.
 #include "kernels.h"
 
@@ -122,6 +123,7 @@ __device__ double heating_fraction(int model, double fel, double rho, double u, 
     const double x = fmax(1.0 - beta / bmax, 0.0);
     return 0.5 * exp(-pow(x, 3.3) / (1.0 + 1.2 * pow(sw, 0.7)));
   }
+  if (model == GRMHD_HEAT_SHARMA) return 1.0 / (1.0 + sqrt(pi / fmax(pe, 1e-300)) / 3.0);
   // Howes
   const double theta = pi / fmax(pe, 1e-300);
   const double lt = log10(theta);

@@ -57,6 +57,7 @@ CASES = {
     "torus_mc_werner": (lambda: problems.fm_torus(n1=40, n2=18, n3=3), el.MODEL_WERNER, 0.0, 6),
     "torus_mc_rowan": (lambda: problems.fm_torus(n1=40, n2=18, n3=3), el.MODEL_ROWAN, 0.0, 6),
     "torus_mc_howes": (lambda: problems.fm_torus(n1=72, n2=20, n3=5), el.MODEL_HOWES, 0.0, 6),
+    "torus_mc_sharma": (lambda: problems.fm_torus(n1=40, n2=18, n3=3), el.MODEL_SHARMA, 0.0, 6),
     "torus_weno5_howes": (lambda: problems.fm_torus(n1=72, n2=20, n3=5, recon=problems.RECON_WENO5),
                           el.MODEL_HOWES, 0.0, 6),
     "bondi_kawazura": (lambda: problems.bondi(n1=37, n2=13, n3=2, a=0.5), el.MODEL_KAWAZURA, 0.0, 10),
@@ -112,7 +113,7 @@ def test_argument_errors(lib):
     prm, P0 = problems.linear_modes(n=8)
     sim = lib.Sim(prm)
     P, E = sim.to_device(P0), sim.to_device(problems.electron_scalars(P0, prm["gam"]))
-    for model, fel in [(5, 0.5), (-1, 0.5), (0, 1.5), (0, -0.1), (0, float("nan"))]:
+    for model, fel in [(6, 0.5), (-1, 0.5), (0, 1.5), (0, -0.1), (0, float("nan"))]:
         with pytest.raises(lib.GrmhdError) as e:
             sim.step_electrons(P, E, 1e-3, model, fel)
         assert e.value.status == lib.GRMHD_EINVAL

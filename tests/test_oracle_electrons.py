@@ -124,7 +124,7 @@ def _sod(n, lam=1.0, gam=5.0 / 3.0, b=0.3):
 
 
 @pytest.mark.parametrize("model", [el.MODEL_CONSTANT, el.MODEL_KAWAZURA, el.MODEL_WERNER,
-                                   el.MODEL_ROWAN, el.MODEL_HOWES])
+                                   el.MODEL_ROWAN, el.MODEL_HOWES, el.MODEL_SHARMA])
 def test_scale_invariance(model):
     # ideal MHD has no density scale: rho, u -> lam rho, lam u and B -> sqrt(lam) B
     # map solutions to solutions, so K_tot -> lam^(1-gamma) K_tot and
@@ -161,7 +161,8 @@ def test_proportional_partition_is_kept_on_the_torus():
     assert np.all(np.isfinite(E1[it]))
 
 
-@pytest.mark.parametrize("model", [el.MODEL_KAWAZURA, el.MODEL_WERNER, el.MODEL_ROWAN, el.MODEL_HOWES])
+@pytest.mark.parametrize("model", [el.MODEL_KAWAZURA, el.MODEL_WERNER, el.MODEL_ROWAN, el.MODEL_HOWES,
+                                   el.MODEL_SHARMA])
 def test_bounds_on_the_torus(model):
     prm, P = problems.fm_torus(n1=32, n2=16, n3=4)
     gam = prm["gam"]
@@ -205,8 +206,11 @@ def test_heating_model_limits():
     # T_i = T_e, Q_i/Q_e -> 0.92 sqrt(m_p / m_e)
     assert _fe(el.MODEL_HOWES, beta=1e-3) == pytest.approx(1.0, abs=1e-12)
     assert _fe(el.MODEL_HOWES, beta=1e6) == pytest.approx(1.0 / (1.0 + 0.92 * np.sqrt(el.MP_ME)), rel=1e-6)
+    # Sharma et al. 2007: Q_i/Q_e = sqrt(T_i/T_e)/3, so 3/4 at T_e = T_i
+    assert _fe(el.MODEL_SHARMA, beta=1.0) == pytest.approx(0.75, rel=1e-12)
+    assert _fe(el.MODEL_SHARMA, beta=1.0, te_ti=0.25) == pytest.approx(0.6, rel=1e-12)
     # all models are fractions
-    for m in (el.MODEL_KAWAZURA, el.MODEL_WERNER, el.MODEL_ROWAN, el.MODEL_HOWES):
+    for m in (el.MODEL_KAWAZURA, el.MODEL_WERNER, el.MODEL_ROWAN, el.MODEL_HOWES, el.MODEL_SHARMA):
         for b in (1e-8, 1e-2, 1.0, 1e2, 1e8):
             for r in (0.01, 1.0, 100.0):
                 f = _fe(m, beta=b, te_ti=r)
