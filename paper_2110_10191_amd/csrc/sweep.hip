@@ -10,7 +10,8 @@
 // Faces covered: 0..n_d along d, and -1..n_t in both transverse directions
 // (the extra transverse layer feeds the Flux-CT EMFs). The per-direction
 // maximum of ctop over the faces with interior transverse index feeds the
-// Courant step (one atomic max per block).
+// Courant step (one atomic max per block); a face with a NaN speed counts as
+// +inf there, which the step reports as a non-finite state.
 #include "kernels.h"
 
 namespace {
@@ -80,8 +81,11 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
     else if (D == 2) inner = (i >= 0 && i < d.n1 && k >= 0 && k < d.n3);
     else inner = (i >= 0 && i < d.n1 && j >= 0 && j < d.n2);
     if (inner) {
-      cmx = (double)ct;
-      if (cmx != cmx) cmx = __builtin_inf();
+      // fmax drops a NaN operand, so a face whose states are not finite would
+      // report a finite (often zero) speed: any NaN speed makes it +inf, so
+      // the Courant step sees the non-finite state
+      const T chk = (cpL + cmL) + (cpR + cmR);
+      cmx = (chk == chk) ? (double)ct : __builtin_inf();
     }
   }
   if (ctop) block_max_to(cmx, ctop + (D - 1));

@@ -63,6 +63,11 @@ class VirtualClock:
 
 # ----------------------------------------------------------------- engines
 
+class JobFailed(RuntimeError):
+    """A job the engine could not start (its initial state has no finite
+    Courant step, or the library refused the problem)."""
+
+
 class GpuEngine:
     """Runs admitted jobs as one batch of the HIP library (same recon and
     precision for every job)."""
@@ -89,13 +94,19 @@ class GpuEngine:
     def start(self, job_id, prm, P0):
         if prm["recon"] != self.recon or prm["precision"] != self.precision:
             raise ValueError("every job of the engine needs its recon and precision")
-        with self.torch.cuda.device(self.device), self.torch.cuda.stream(self.stream):
-            sim = self.B.Sim(prm, device=self.device, stream=self.stream)
-            if self.tiles:
-                sim.set_tiles("sweep", *self.tiles["sweep"])
-                sim.set_tiles("update", *self.tiles["update"])
-            P = sim.to_device(P0)
-            dt = sim.get_dt(P)
+        sim = None
+        try:
+            with self.torch.cuda.device(self.device), self.torch.cuda.stream(self.stream):
+                sim = self.B.Sim(prm, device=self.device, stream=self.stream)
+                if self.tiles:
+                    sim.set_tiles("sweep", *self.tiles["sweep"])
+                    sim.set_tiles("update", *self.tiles["update"])
+                P = sim.to_device(P0)
+                dt = sim.get_dt(P)
+        except self.B.GrmhdError as e:
+            if sim is not None:
+                sim.close()
+            raise JobFailed(str(e)) from e
         self.jobs[job_id] = [sim, P, dt]
         self.dirty = True
 
@@ -159,8 +170,10 @@ class FakeEngine:
     """Same interface, no device: a step of a job costs zones / rate seconds of
     a virtual clock. For testing the scheduler."""
 
-    def __init__(self, clock, rate=1e9, bytes_per_zone=200, overhead=0.0):
+    def __init__(self, clock, rate=1e9, bytes_per_zone=200, overhead=0.0, fail_at=None):
         self.clock = clock
+        self.fail_at = dict(fail_at or {})   # job id -> step count from which its status is 1
+                                             # (-1: the job cannot start)
         self.rate = rate
         self.bytes_per_zone = bytes_per_zone
         self.overhead = overhead
@@ -173,6 +186,8 @@ class FakeEngine:
         return prm["n1"] * prm["n2"] * prm["n3"] * self.bytes_per_zone
 
     def start(self, job_id, prm, P0):
+        if self.fail_at.get(job_id) == -1:
+            raise JobFailed(f"job {job_id}: no finite Courant step")
         self.jobs[job_id] = prm
         self.steps[job_id] = 0
 
@@ -188,7 +203,7 @@ class FakeEngine:
         self.pending = 0.0
 
     def status(self):
-        return {j: 0 for j in self.jobs}
+        return {j: int(j in self.fail_at and self.steps[j] >= self.fail_at[j]) for j in self.jobs}
 
     def finish(self, job_id, keep=False):
         self.jobs.pop(job_id)
@@ -198,7 +213,7 @@ class FakeEngine:
 # ----------------------------------------------------------------- scheduler
 
 class Record:
-    __slots__ = ("spec", "prm", "state", "bytes", "admitted", "done", "left", "failed", "result")
+    __slots__ = ("spec", "prm", "state", "bytes", "admitted", "done", "left", "failed", "result", "error")
 
     def __init__(self, spec):
         self.spec = spec
@@ -210,6 +225,7 @@ class Record:
         self.left = spec.steps
         self.failed = False
         self.result = None
+        self.error = None
 
 
 def percentile(values, q):
@@ -278,7 +294,15 @@ class Server:
                 if self.in_use + r.bytes > self.budget:
                     break
                 queue.popleft()
-                self.engine.start(r.spec.id, r.prm, r.state)
+                try:
+                    self.engine.start(r.spec.id, r.prm, r.state)
+                except JobFailed as e:
+                    # retired at once; the other jobs never see it
+                    r.state = None
+                    r.admitted = r.done = self.clock.now()
+                    r.failed = True
+                    r.error = str(e)
+                    continue
                 r.state = None
                 r.admitted = self.clock.now()
                 self.in_use += r.bytes
@@ -301,17 +325,20 @@ class Server:
             self.engine.sync()
             self.cycles += 1
             now = self.clock.now()
-            finished = [r for r in running.values() if r.left - n <= 0]
             for r in running.values():
                 r.left -= n
-            if finished:
-                status = self.engine.status()
-                for r in finished:
-                    r.failed = bool(status.get(r.spec.id, 0))
-                    r.result = self.engine.finish(r.spec.id, keep=r.spec.id in self.keep)
-                    r.done = now
-                    self.in_use -= r.bytes
-                    del running[r.spec.id]
+            # a job whose signal speeds went non-finite is retired now, with
+            # an error, instead of running out its step count
+            status = self.engine.status()
+            finished = [r for r in running.values() if r.left <= 0 or status.get(r.spec.id, 0)]
+            for r in finished:
+                if status.get(r.spec.id, 0):
+                    r.failed = True
+                    r.error = "non-finite signal speed"
+                r.result = self.engine.finish(r.spec.id, keep=r.spec.id in self.keep)
+                r.done = now
+                self.in_use -= r.bytes
+                del running[r.spec.id]
             if self.progress:
                 self.progress(self, now, len(running), len(queue),
                               sum(1 for r in recs if r.done is not None))
@@ -323,13 +350,16 @@ class Report:
         self.recs = recs
         self.rejected = rejected
         done = [r for r in recs if r.admitted is not None]
-        self.latency = [r.done - r.spec.arrival for r in done]
-        self.wait = [r.admitted - r.spec.arrival for r in done]
-        self.work = sum(r.spec.zones * r.spec.steps for r in done)
+        ok = [r for r in done if not r.failed]
+        # latency, wait and work of the jobs that completed (ok order)
+        self.latency = [r.done - r.spec.arrival for r in ok]
+        self.wait = [r.admitted - r.spec.arrival for r in ok]
+        self.work = sum(r.spec.zones * r.spec.steps for r in ok)
         t_first = min((r.spec.arrival for r in recs), default=0.0)
         t_last = max((r.done for r in done), default=0.0)
         self.makespan = t_last - t_first if done else 0.0
         self.failed = [r.spec.id for r in done if r.failed]
+        self.errors = {r.spec.id: r.error for r in done if r.failed}
         self.server = server
 
     def results(self):

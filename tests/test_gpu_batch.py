@@ -171,3 +171,51 @@ def test_profiled_batch_steps_equal_graph_replays(lib):
         sim.close()
     assert outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][0], outs[1][0])
+
+
+@pytest.mark.parametrize("var", [1, 5], ids=["nan_u", "nan_B1"])
+def test_a_non_finite_zone_in_one_job_leaves_the_others_untouched(lib, var):
+    """Fault injection: one zone of one job holds a NaN. A NaN internal energy
+    only poisons hydrodynamic fluxes: the inversions around it fail and the
+    fixup repairs them, so the job goes on with a finite state. A NaN field
+    component poisons the EMFs, which the fixup does not touch: the job's
+    signal speeds go non-finite, its status is raised and its step size stops
+    growing. Either way every other job of the batch evolves bit for bit as
+    without it."""
+    jobs = job_set()
+    clean, dts_clean, st = run_batch(lib, jobs, 3)
+    assert st == [0] * len(jobs)
+    sims = [lib.Sim(prm) for prm, _ in jobs]
+    dt0 = [s.get_dt(s.to_device(P0)) for s, (_, P0) in zip(sims, jobs)]
+    for s in sims:
+        s.close()
+    bad = list(jobs)
+    prm, P0 = bad[2]
+    P0 = P0.copy()
+    P0[var, NG + 1, NG + 5, NG + 10] = np.nan
+    bad[2] = (prm, P0)
+    outs, dts, status = run_batch(lib, bad, 3, dt0=dt0)
+    for j in (0, 1, 3):
+        assert np.array_equal(outs[j], clean[j]), j
+        assert dts[j] == dts_clean[j]
+    if var == 1:
+        assert status == [0, 0, 0, 0]
+        assert np.isfinite(interior(outs[2], prm)).all()
+    else:
+        assert status == [0, 0, 1, 0]
+        assert dts[2] == dt0[2]
+
+
+def test_a_non_finite_state_is_an_error_of_the_step(lib):
+    prm, P0 = problems.fm_torus(n1=48, n2=28, n3=4)
+    sim = lib.Sim(prm)
+    P = sim.to_device(P0)
+    dt = sim.get_dt(P)
+    P[5, NG + 1, NG + 5, NG + 10] = float("nan")
+    with pytest.raises(lib.GrmhdError) as e:
+        sim.step(P, dt)
+    assert e.value.status == lib.GRMHD_ESTATE
+    with pytest.raises(lib.GrmhdError) as e:
+        sim.get_dt(P)
+    assert e.value.status == lib.GRMHD_ESTATE
+    sim.close()

@@ -47,6 +47,33 @@ def test_stream_matches_jobs_run_alone(lib, recon, precision):
     assert ident == {s.id: True for s in specs}
 
 
+def test_a_job_that_cannot_start_is_failed_and_the_others_are_untouched(lib):
+    """Fault injection: a job whose initial state holds a NaN has no finite
+    Courant step; the server retires it at admission with the library's error
+    and every other job still ends bit for bit as when run alone."""
+    specs = [
+        JobSpec(0, "torus", 48, 32, 8, a=0.9, steps=6, arrival=0.0),
+        JobSpec(1, "bondi", 40, 24, 4, a=0.3, steps=5, arrival=0.0),
+        JobSpec(2, "torus", 32, 24, 4, a=0.5, steps=4, arrival=0.0),
+    ]
+    clean = make_state(problems.RECON_MC, problems.FP64)
+
+    def mk(spec):
+        prm, P0 = clean(spec)
+        if spec.id == 1:
+            P0 = P0.copy()
+            P0[1, 4, 8, 12] = np.nan
+        return prm, P0
+
+    eng = GpuEngine(problems.RECON_MC, problems.FP64)
+    srv = Server(eng, mk, 1 << 40, quantum=2, keep=[0, 2])
+    rep = srv.run(specs)
+    assert rep.failed == [1] and "status -5" in rep.errors[1]
+    assert rep.summary()["completed"] == 2 and srv.in_use == 0
+    ident = identity_check(rep, specs, clean, problems.RECON_MC, problems.FP64, [0, 2])
+    assert ident == {0: True, 2: True}
+
+
 def test_tuned_tiles_do_not_change_a_served_job(lib):
     spec = JobSpec(0, "torus", 48, 32, 8, a=0.9, steps=4)
     mk = make_state(problems.RECON_MC, problems.FP64)

@@ -14,9 +14,9 @@ def fake_state(spec):
     return prm, None
 
 
-def serve(specs, budget, quantum=25, rate=1e9, bytes_per_zone=1, overhead=0.0):
+def serve(specs, budget, quantum=25, rate=1e9, bytes_per_zone=1, overhead=0.0, fail_at=None):
     clock = VirtualClock()
-    eng = FakeEngine(clock, rate=rate, bytes_per_zone=bytes_per_zone, overhead=overhead)
+    eng = FakeEngine(clock, rate=rate, bytes_per_zone=bytes_per_zone, overhead=overhead, fail_at=fail_at)
     srv = Server(eng, fake_state, budget, clock=clock, quantum=quantum, keep=[s.id for s in specs])
     rep = srv.run(specs)
     return rep, eng, srv
@@ -74,6 +74,33 @@ def test_oversized_job_is_rejected_not_hung():
     rep, eng, _ = serve(specs, budget=10_000)
     assert [r.spec.id for r in rep.rejected] == [0]
     assert eng.steps == {1: 5}
+
+
+def test_a_job_that_cannot_start_is_failed_and_frees_nothing():
+    specs = [JobSpec(0, "box", 100, 100, 100, steps=100), JobSpec(1, "box", 100, 100, 100, steps=100),
+             JobSpec(2, "box", 100, 100, 100, steps=100)]
+    rep, eng, srv = serve(specs, budget=1_000_000, fail_at={1: -1})
+    assert rep.failed == [1] and "Courant" in rep.errors[1]
+    assert eng.steps == {0: 100, 2: 100}
+    # job 1 is tried when job 0 frees the budget, fails at once and takes no
+    # time: job 2 follows job 0 directly
+    lat = {r.spec.id: r.done - r.spec.arrival for r in rep.recs}
+    assert lat[0] == pytest.approx(0.1) and lat[1] == pytest.approx(0.1) and lat[2] == pytest.approx(0.2)
+    s = rep.summary()
+    assert s["completed"] == 2 and s["failed"] == 1
+    assert s["zone_cycles_per_s"] == pytest.approx(1e9)
+    assert srv.in_use == 0
+
+
+def test_a_job_that_goes_non_finite_is_retired_at_once():
+    # job 0 reports a non-finite speed from step 10 on; cycles are 4 steps, so
+    # it is retired after the cycle that reaches step 12, not after 100 steps
+    specs = [JobSpec(0, "box", 10, 10, 10, steps=100), JobSpec(1, "box", 10, 10, 10, steps=20)]
+    rep, eng, srv = serve(specs, budget=10**9, quantum=4, fail_at={0: 10})
+    res = rep.results()
+    assert res[0] == ("state", 0, 12) and res[1] == ("state", 1, 20)
+    assert rep.failed == [0] and rep.errors[0] == "non-finite signal speed"
+    assert rep.summary()["completed"] == 1 and srv.in_use == 0
 
 
 def test_percentile_is_nearest_rank():
