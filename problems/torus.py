@@ -1,4 +1,5 @@
-"""Fishbone-Moncrief torus in Kerr, on a funky-MKS grid.
+"""Fishbone-Moncrief torus in Kerr, on a funky-MKS grid (or plain MKS with
+``coords=KERR_MKS``).
 
 The accretion-torus problem of the Scaling section. Units GM = c = 1 and the
 density normalised to a maximum of 1 (Implementation Notes section).
@@ -44,10 +45,11 @@ def fm_lnh(r, th, a, ell, rin):
 
 
 def fm_torus(n1=288, n2=128, n3=128, a=0.9375, rin=6.0, rmax=12.0, gam=13.0 / 9.0,
-             r_out=1000.0, beta=100.0, seed=2, noise=0.04, recon=RECON_MC, precision=FP64):
+             r_out=1000.0, beta=100.0, seed=2, noise=0.04, recon=RECON_MC, precision=FP64,
+             coords=KERR_FMKS, hslope=0.3):
     x1min, x1max = kerr_grid_extent(n1, a, r_out)
     prm = base_problem(
-        n1, n2, n3, coords=KERR_FMKS, a=a, gam=gam,
+        n1, n2, n3, coords=coords, a=a, gam=gam, hslope=hslope,
         x1min=x1min, x1max=x1max, x2min=0.0, x2max=1.0, x3min=0.0, x3max=2.0 * math.pi,
         bc=[[BC_OUTFLOW, BC_OUTFLOW], [BC_POLAR, BC_POLAR], [BC_PERIODIC, BC_PERIODIC]],
         floors=1, recon=recon, precision=precision,

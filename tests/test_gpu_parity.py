@@ -152,6 +152,16 @@ def test_torus_weno5_fp64(lib):
     assert (err <= 1e-10).all(), err
 
 
+def test_torus_plain_mks_fp64(lib):
+    """The torus on a plain MKS grid (theta = pi x2 + (1 - h)/2 sin 2 pi x2, h = 0.3)."""
+    prm, P0 = problems.fm_torus(n1=72, n2=40, n3=6, coords=problems.KERR_MKS)
+    ref, dts = oracle_run(prm, P0, 10)
+    got = gpu_run(lib, prm, P0, dts)
+    err = rel_l1(interior(got, prm), interior(ref, prm))
+    print("torus MKS rel-L1", err)
+    assert (err <= 1e-10).all(), err
+
+
 def test_bondi_dirichlet_2d(lib):
     prm, P0 = problems.bondi(n1=68, n2=36, n3=1, a=0.5)
     ref, dts = oracle_run(prm, P0, 10)

@@ -30,6 +30,29 @@ def test_fmks_theta_endpoints_and_monotone():
     assert np.allclose(d1, n1, atol=1e-8) and np.allclose(d2, n2, atol=1e-7)
 
 
+def test_mks_theta_map():
+    # plain MKS: theta(0) = 0, theta(1/2) = pi/2, theta(1) = pi, mirror symmetry
+    # about the equator, monotone for 0 < h <= 1, independent of x1; h = 1 is
+    # the uniform map theta = pi x2 of exponential Kerr-Schild coordinates
+    prm = problems.fm_torus(n1=16, n2=16, n3=1, coords=problems.KERR_MKS)[0]
+    assert prm["coords"] == problems.KERR_MKS and prm["hslope"] == 0.3
+    x2 = np.linspace(0.0, 1.0, 1001)
+    for x1 in (prm["x1min"], 2.0):
+        th, d1, d2 = G.theta_of(np.full_like(x2, x1), x2, prm)
+        assert abs(th[0]) < 1e-15 and abs(th[500] - np.pi / 2) < 1e-15 and abs(th[-1] - np.pi) < 1e-15
+        assert np.allclose(th + th[::-1], np.pi, atol=1e-14)
+        assert (np.diff(th) > 0).all() and (d1 == 0).all()
+        h = 1e-6
+        num = (G.theta_of(np.full_like(x2, x1), x2 + h, prm)[0] - G.theta_of(np.full_like(x2, x1), x2 - h, prm)[0]) / (2 * h)
+        assert np.allclose(d2, num, atol=1e-7)
+    # d theta / d x2 is (2 - h) pi at the poles and h pi at the equator: MKS
+    # concentrates zones toward the equator
+    assert d2[0] / d2[500] == pytest.approx((2.0 - 0.3) / 0.3, rel=1e-12)
+    ks = dict(prm, hslope=1.0)
+    th, _, d2 = G.theta_of(np.full_like(x2, 1.0), x2, ks)
+    assert np.allclose(th, np.pi * x2, rtol=0, atol=4e-16) and np.allclose(d2, np.pi, rtol=1e-15)
+
+
 def test_horizon_rule():
     prm = torus_prm()
     a = prm["a"]
