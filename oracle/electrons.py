@@ -67,12 +67,14 @@ MP_ME = 1836.15267343
 MODEL_CONSTANT, MODEL_KAWAZURA, MODEL_WERNER, MODEL_ROWAN, MODEL_HOWES, MODEL_SHARMA = 0, 1, 2, 3, 4, 5
 
 
-def fill_scalar_ghosts(E, grid):
-    """Ghost zones of a padded scalar array, in place (E1)."""
+def fill_scalar_ghosts(E, grid, do_x3=True):
+    """Ghost zones of a padded scalar array, in place (E1). With
+    ``do_x3=False`` the x3 ghosts are real neighbour data of a window and are
+    left alone."""
     prm = grid.prm
     n1, n2, n3 = grid.n
     bc = prm["bc"]
-    K = slice(NG, NG + n3)
+    K = slice(NG, NG + E.shape[1] - 2 * NG)
     J = slice(NG, NG + n2)
     for side in (0, 1):
         t = bc[0][side]
@@ -99,7 +101,7 @@ def fill_scalar_ghosts(E, grid):
                 continue
             E[:, K, g, :] = E[:, K, s, :]
     for side in (0, 1):
-        t = bc[2][side]
+        t = bc[2][side] if do_x3 else BC_DIRICHLET
         for m in range(NG):
             g = NG - 1 - m if side == 0 else NG + n3 + m
             if t == BC_PERIODIC:
@@ -169,7 +171,8 @@ def electron_substep(Es, Eb, Pb, Pn, mass, grid, dt, model, fel):
     E4). Returns the new scalars on the interior."""
     prm = grid.prm
     gam = prm["gam"]
-    n1, n2, n3 = grid.n
+    n1, n2 = grid.n[0], grid.n[1]
+    n3 = Pn.shape[1]                # the block's x3 extent (a window of the domain, or all of it)
     K, J, I = slice(NG, NG + n3), slice(NG, NG + n2), slice(NG, NG + n1)
     Kp, Jp, Ip = slice(NG + 1, NG + n3 + 1), slice(NG + 1, NG + n2 + 1), slice(NG + 1, NG + n1 + 1)
     F1 = scalar_fluxes(Es, mass[0], grid, 1)
@@ -220,3 +223,30 @@ def step(P, E, grid, dt, model=MODEL_CONSTANT, fel=0.5):
     En[it] = En_i
     return Pn, En, dt_from_ctop(cmax, grid)
 
+
+
+def step_window(P, E, grid, dt, k0, k1, model=MODEL_CONSTANT, fel=0.5):
+    """(P^{n+1}, E^{n+1}) on interior slabs k0..k1-1 of full padded states,
+    computed from a window of x3 slabs around them, as the fluid window step
+    does (the scalars need no wider margin than the fluid: their face values
+    use the same stencil and their fluxes the fluid's mass fluxes)."""
+    n1, n2, n3 = grid.n
+    full = fill_ghosts(P.copy(), grid)
+    fullE = fill_scalar_ghosts(E.copy(), grid)
+    M1 = 5
+    ks = np.arange(k0 - M1 - NG, k1 + M1 + NG) % n3 + NG
+    blk, eblk = full[:, ks], fullE[:, ks]
+    it1 = (slice(None), slice(NG, blk.shape[1] - NG), slice(NG, NG + n2), slice(NG, NG + n1))
+    Ph_i, _, _, m1 = substep(blk, blk[it1], grid, 0.5 * dt, mass_flux=True)
+    Eh_i = electron_substep(eblk, eblk[it1], blk[it1], Ph_i, m1, grid, 0.5 * dt, model, fel)
+    ph, eh = blk.copy(), eblk.copy()
+    ph[it1], eh[it1] = Ph_i, Eh_i
+    fill_ghosts(ph, grid, do_x3=False)
+    fill_scalar_ghosts(eh, grid, do_x3=False)
+    off = (M1 + NG) - (1 + NG)
+    w = (k1 - k0) + 2 + 2 * NG
+    blk2, eblk2 = ph[:, off:off + w], eh[:, off:off + w]
+    inner = (slice(None), slice(off + NG, off + NG + (k1 - k0) + 2), slice(NG, NG + n2), slice(NG, NG + n1))
+    Pn_i, _, _, m2 = substep(blk2, blk[inner], grid, dt, mass_flux=True)
+    En_i = electron_substep(eblk2, eblk[inner], blk[inner], Pn_i, m2, grid, dt, model, fel)
+    return Pn_i[:, 1:-1], En_i[:, 1:-1]

@@ -123,3 +123,25 @@ def test_argument_errors(lib):
         sim.step_electrons(P, E, 0.0)
     sim.step_electrons(P, E, 1e-3, "howes", 7.0)      # fel is ignored by the models
     sim.close()
+
+
+def test_full_size_torus_sampled_slabs(lib):
+    """The benchmark's electron configuration (288 x 128 x 128 FMKS torus, MC,
+    FP64, host-driven grmhd_step_electrons, default tiles), Howes model: one
+    GPU step compared on two x3 slabs (one at the periodic seam) that the
+    oracle computes from windows of the same initial state."""
+    prm, P0 = problems.fm_torus()
+    E0 = problems.electron_scalars(P0, prm["gam"], te_ti=0.5)
+    g = oracle.Grid(prm)
+    dt = 0.005
+    sim = lib.Sim(prm)
+    P, E = sim.to_device(P0), sim.to_device(E0)
+    sim.step_electrons(P, E, dt, el.MODEL_HOWES, 0.0, want_dt_next=False)
+    Pg, Eg = interior(sim.to_host(P), prm), interior(sim.to_host(E), prm)
+    sim.close()
+    for k0 in (0, 77):
+        Pr, Er = el.step_window(P0, E0, g, dt, k0, k0 + 1, el.MODEL_HOWES, 0.0)
+        eP = rel_l1(Pg[:, k0:k0 + 1], Pr)
+        eE = rel_l1(Eg[:, k0:k0 + 1], Er)
+        print("slab", k0, eP.max(), eE)
+        assert eP.max() <= 1e-10 and eE.max() <= 1e-10, (k0, eP, eE)

@@ -215,3 +215,18 @@ def test_heating_model_limits():
             for r in (0.01, 1.0, 100.0):
                 f = _fe(m, beta=b, te_ti=r)
                 assert 0.0 <= f <= 1.0, (m, b, r, f)
+
+
+def test_window_step_equals_the_full_step():
+    # the x3-window electron step used for sampled full-size parity returns
+    # the full-domain step's values on its slabs (one at the periodic seam)
+    prm, P = problems.fm_torus(n1=24, n2=12, n3=20)
+    E = problems.electron_scalars(P, prm["gam"], te_ti=0.5)
+    g = oracle.Grid(prm)
+    dt = oracle.get_dt(P, g)
+    Pf, Ef, _ = el.step(P, E, g, dt, el.MODEL_KAWAZURA, 0.0)
+    it = _interior(prm)
+    for k0, k1 in ((0, 1), (7, 9), (19, 20)):
+        Pw, Ew = el.step_window(P, E, g, dt, k0, k1, el.MODEL_KAWAZURA, 0.0)
+        assert np.array_equal(Pw, Pf[it][:, k0:k1]), k0
+        assert np.array_equal(Ew, Ef[it][:, k0:k1]), k0
