@@ -239,8 +239,8 @@ def main():
                     help="device: grmhd_run, the step size kept on the device (default); host: one "
                          "grmhd_step per step with dt read back each step")
     ap.add_argument("--electrons", choices=["constant", "kawazura", "werner", "rowan", "howes", "sharma"], default=None,
-                    help="step the electron entropies too (grmhd_step_electrons, host-driven dt) with "
-                         "this heating model (constant: f_e = 0.5)")
+                    help="step the electron entropies too (grmhd_run_electrons, or grmhd_step_electrons "
+                         "with --path host) with this heating model (constant: f_e = 0.5)")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="also run one plain device copy of this size (for counter scaling)")
     args = ap.parse_args()
@@ -275,9 +275,23 @@ def main():
 
     dt = sim.get_dt(P)
     kernels = {}
-    if args.electrons:
-        # the fluid step plus the three electron passes per substep; one
-        # grmhd_step_electrons call per step, dt read back every step
+    if args.electrons and args.path == "device":
+        # the fluid step plus the three electron passes per substep, through
+        # grmhd_run_electrons (the step size kept on the device)
+        E = sim.to_device(problems.electron_scalars(P0, prm["gam"]))
+        dt = sim.run_electrons(P, E, args.warmup, dt, args.electrons)
+        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
+        g.grmhd_profile(sim.ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        dt = sim.run_electrons(P, E, args.steps, dt, args.electrons)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        g.grmhd_profile(sim.ctx, False)
+        for name in g.KERNELS:
+            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
+    elif args.electrons:
+        # one grmhd_step_electrons call per step, dt read back every step
         E = sim.to_device(problems.electron_scalars(P0, prm["gam"]))
         for _ in range(args.warmup):
             dt = min(sim.step_electrons(P, E, dt, args.electrons), 1.3 * dt)
@@ -396,7 +410,7 @@ def main():
         "config": {"workload": workload,
                    "grid": [n1, n2, n3], "a": prm["a"], "recon": args.recon,
                    "precision": args.precision, "coords": "fmks", "r_out": 1000.0,
-                   "driver": "host" if args.electrons else args.path,
+                   "driver": args.path,
                    "electrons": args.electrons},
         "roofline": roofline,
         "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kernels.items()},

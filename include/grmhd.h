@@ -206,6 +206,12 @@ enum {
 };
 GRMHD_API int grmhd_step_electrons(grmhd_ctx *ctx, double *P, double *E, double dt, int32_t model, double fel,
                                    double *dt_next);
+/* nsteps such steps with the step size kept on the device, as grmhd_run does
+ * for grmhd_step (same rule, same results as a host loop of dt <- min(dt_next,
+ * 1.3 dt) around grmhd_step_electrons). dt (host, in/out) as for grmhd_run;
+ * errors as grmhd_run and grmhd_step_electrons. */
+GRMHD_API int grmhd_run_electrons(grmhd_ctx *ctx, double *P, double *E, int32_t nsteps, double *dt, int32_t model,
+                                  double fel);
 
 /* max |div B| over cell corners, with div B the corner-centred divergence of
  * sqrt(-g) B (the quantity Flux-CT keeps at round-off, Implementation Notes).
@@ -218,9 +224,9 @@ GRMHD_API int grmhd_divb(grmhd_ctx *ctx, const double *P, double *max_divb);
 GRMHD_API int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
 
 /* Kernel timing for measurement. grmhd_profile(ctx, 1) clears the record and
- * starts bracketing every kernel launch of grmhd_step, grmhd_step_electrons
- * (GRMHD_K_ELECTRONS: the scalar ghosts, advection and heating) and grmhd_run with HIP events on the
- * context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
+ * starts bracketing every kernel launch of grmhd_step, grmhd_run and the
+ * electron calls (GRMHD_K_ELECTRONS: the scalar ghosts, advection and
+ * heating) with HIP events on the context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
  * one kernel class, the summed device time in ms and the launch count since
  * the last clear; synchronises. Timing adds two event records per launch. */
 enum {

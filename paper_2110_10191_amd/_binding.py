@@ -14,7 +14,7 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 # every symbol include/grmhd.h declares
 EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
-    "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_speeds", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
+    "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_speeds", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
@@ -82,6 +82,7 @@ def _load():
         "grmhd_get_dt": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step": ([vp, vp, ctypes.c_double, dp], ctypes.c_int),
         "grmhd_step_electrons": ([vp, vp, vp, ctypes.c_double, i32, ctypes.c_double, dp], ctypes.c_int),
+        "grmhd_run_electrons": ([vp, vp, vp, i32, dp, i32, ctypes.c_double], ctypes.c_int),
         "grmhd_run": ([vp, vp, i32, dp], ctypes.c_int),
         "grmhd_fill_ghosts": ([vp, vp, vp], ctypes.c_int),
         "grmhd_substep": ([vp, vp, vp, vp, ctypes.c_double, i32], ctypes.c_int),
@@ -199,6 +200,14 @@ def grmhd_step_electrons(ctx, P, E, dt, model=0, fel=0.5, want_dt_next=True):
     _check(lib.grmhd_step_electrons(ctx, _ptr(P), _ptr(E), float(dt), m, float(fel),
                                     ctypes.byref(dn) if want_dt_next else None), ctx)
     return dn.value if want_dt_next else None
+
+
+def grmhd_run_electrons(ctx, P, E, nsteps, dt, model=0, fel=0.5):
+    """nsteps electron steps with the step size kept on the device; returns the next dt."""
+    m = HEAT_MODELS[model] if isinstance(model, str) else int(model)
+    d = ctypes.c_double(float(dt))
+    _check(lib.grmhd_run_electrons(ctx, _ptr(P), _ptr(E), int(nsteps), ctypes.byref(d), m, float(fel)), ctx)
+    return d.value
 
 
 def grmhd_run(ctx, P, nsteps, dt):
@@ -430,6 +439,9 @@ class Sim:
 
     def step_electrons(self, P, E, dt, model=0, fel=0.5, want_dt_next=True):
         return grmhd_step_electrons(self.ctx, P, E, dt, model, fel, want_dt_next)
+
+    def run_electrons(self, P, E, nsteps, dt, model=0, fel=0.5):
+        return grmhd_run_electrons(self.ctx, P, E, nsteps, dt, model, fel)
 
     def divb(self, P):
         return grmhd_divb(self.ctx, P)

@@ -129,7 +129,7 @@ struct ElectronPass {
 // predictor or corrector substep; Pb is the base state (also the source of
 // Dirichlet ghosts). dt_dev: when not null the step is dt_scale * *dt_dev (read
 // on the device). fill = false leaves the ghost zones of Ps as they are.
-// el: also advect and heat the electron entropies (host dt only).
+// el: also advect and heat the electron entropies.
 int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop,
             const double* dt_dev = nullptr, double dt_scale = 1.0, bool fill = true,
             const ElectronPass* el = nullptr) {
@@ -153,7 +153,7 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
     // before the update: in the corrector it overwrites the base state in place
     ProfScope ps(c->prof, s, GRMHD_K_ELECTRONS);
     HIP_OR_FAIL(c, launch_scalar_advect(c->mixed, c->p.recon, c->d, c->t, c->up, c->F[0], c->F[1], c->F[2], Pb,
-                                        el->Eb, el->Es, c->Uk, dt, s),
+                                        el->Eb, el->Es, c->Uk, dt, dt_dev, dt_scale, s),
                 "scalar advection");
   }
   {
@@ -191,6 +191,60 @@ int read_dt(grmhd_ctx* c, double* dt) {
   double sum = 0.0;
   for (int d = 0; d < 3; ++d) sum += v[d] / c->dx[d];
   *dt = sum > 0.0 ? c->p.cfl / sum : INFINITY;
+  return GRMHD_OK;
+}
+
+// argument checks of the electron calls, and their scratch on first use
+int electron_prep(grmhd_ctx* ctx, const double* P, const double* E, int32_t model, double fel, const char* who) {
+  std::string w(who);
+  if (!P || !E) return fail(ctx, GRMHD_EINVAL, w + ": NULL state");
+  if (model < GRMHD_HEAT_CONSTANT || model > GRMHD_HEAT_SHARMA)
+    return fail(ctx, GRMHD_EINVAL, w + ": unknown heating model");
+  if (model == GRMHD_HEAT_CONSTANT && !(fel >= 0.0 && fel <= 1.0))
+    return fail(ctx, GRMHD_EINVAL, w + ": fel must lie in [0, 1]");
+  if (!ctx->Eh) {
+    const size_t bytes = (size_t)GRMHD_NSCALAR * ctx->d.sv * sizeof(double);
+    if (dalloc(&ctx->Eh, bytes) != hipSuccess || dalloc(&ctx->Uk, bytes) != hipSuccess) {
+      if (ctx->Eh) (void)hipFree(ctx->Eh);
+      if (ctx->Uk) (void)hipFree(ctx->Uk);
+      ctx->Eh = ctx->Uk = nullptr;
+      return fail(ctx, GRMHD_ENOMEM, w + ": scratch allocation failed");
+    }
+    // ghost and padding zones of the half-step entropies that no rule writes stay finite
+    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->Eh, 0, bytes, ctx->stream), "clear scratch");
+  }
+  return GRMHD_OK;
+}
+
+// nsteps steps with the step size kept on the device (E, model, fel: with
+// electron heating when E is not null)
+int run_steps(grmhd_ctx* ctx, double* P, double* E, int32_t model, double fel, int32_t nsteps, double* dt) {
+  struct {
+    double dt;
+    int status;
+  } host{*dt, 0};
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&ctx->ctr->dt, &host.dt, sizeof(double), hipMemcpyHostToDevice, ctx->stream),
+              "set dt");
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&ctx->ctr->status, &host.status, sizeof(int), hipMemcpyHostToDevice, ctx->stream),
+              "set status");
+  const double* dtp = &ctx->ctr->dt;
+  const ElectronPass pred{E, E, ctx->Eh, model, fel};
+  const ElectronPass corr{ctx->Eh, E, E, model, fel};
+  for (int s = 0; s < nsteps; ++s) {
+    HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 8, ctx->stream), "reset");
+    int st = substep(ctx, P, P, ctx->Ph, 0.0, false, dtp, 0.5, true, E ? &pred : nullptr);
+    if (st != GRMHD_OK) return st;
+    st = substep(ctx, ctx->Ph, P, P, 0.0, true, dtp, 1.0, true, E ? &corr : nullptr);
+    if (st != GRMHD_OK) return st;
+    HIP_OR_FAIL(ctx, launch_ctx_dt(ctx->ctr, ctx->p.cfl, ctx->dx[0], ctx->dx[1], ctx->dx[2], ctx->stream), "dt");
+  }
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.dt, &ctx->ctr->dt, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
+              "read dt");
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.status, &ctx->ctr->status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
+              "read status");
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
+  *dt = host.dt;
+  if (host.status) return fail(ctx, GRMHD_ESTATE, "non-finite signal speed in the state");
   return GRMHD_OK;
 }
 
@@ -438,26 +492,12 @@ int grmhd_step(grmhd_ctx* ctx, double* P, double dt, double* dt_next) {
 int grmhd_step_electrons(grmhd_ctx* ctx, double* P, double* E, double dt, int32_t model, double fel,
                          double* dt_next) {
   if (!ctx) return GRMHD_EINVAL;
-  if (!P || !E) return fail(ctx, GRMHD_EINVAL, "step_electrons: NULL state");
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GRMHD_EINVAL, "step_electrons: dt must be finite and > 0");
-  if (model < GRMHD_HEAT_CONSTANT || model > GRMHD_HEAT_SHARMA)
-    return fail(ctx, GRMHD_EINVAL, "step_electrons: unknown heating model");
-  if (model == GRMHD_HEAT_CONSTANT && !(fel >= 0.0 && fel <= 1.0))
-    return fail(ctx, GRMHD_EINVAL, "step_electrons: fel must lie in [0, 1]");
-  if (!ctx->Eh) {
-    const size_t bytes = (size_t)GRMHD_NSCALAR * ctx->d.sv * sizeof(double);
-    if (dalloc(&ctx->Eh, bytes) != hipSuccess || dalloc(&ctx->Uk, bytes) != hipSuccess) {
-      if (ctx->Eh) (void)hipFree(ctx->Eh);
-      if (ctx->Uk) (void)hipFree(ctx->Uk);
-      ctx->Eh = ctx->Uk = nullptr;
-      return fail(ctx, GRMHD_ENOMEM, "step_electrons: scratch allocation failed");
-    }
-    // ghost and padding zones of the half-step entropies that no rule writes stay finite
-    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->Eh, 0, bytes, ctx->stream), "clear scratch");
-  }
+  int st = electron_prep(ctx, P, E, model, fel, "step_electrons");
+  if (st != GRMHD_OK) return st;
   HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 8, ctx->stream), "reset");
   const ElectronPass pred{E, E, ctx->Eh, model, fel};
-  int st = substep(ctx, P, P, ctx->Ph, 0.5 * dt, false, nullptr, 1.0, true, &pred);
+  st = substep(ctx, P, P, ctx->Ph, 0.5 * dt, false, nullptr, 1.0, true, &pred);
   if (st != GRMHD_OK) return st;
   const ElectronPass corr{ctx->Eh, E, E, model, fel};
   st = substep(ctx, ctx->Ph, P, P, dt, true, nullptr, 1.0, true, &corr);
@@ -471,31 +511,18 @@ int grmhd_run(grmhd_ctx* ctx, double* P, int32_t nsteps, double* dt) {
   if (!P || !dt) return fail(ctx, GRMHD_EINVAL, "run: NULL argument");
   if (nsteps < 0) return fail(ctx, GRMHD_EINVAL, "run: nsteps < 0");
   if (!(*dt > 0.0) || !std::isfinite(*dt)) return fail(ctx, GRMHD_EINVAL, "run: dt must be finite and > 0");
-  struct {
-    double dt;
-    int status;
-  } host{*dt, 0};
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(&ctx->ctr->dt, &host.dt, sizeof(double), hipMemcpyHostToDevice, ctx->stream),
-              "set dt");
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(&ctx->ctr->status, &host.status, sizeof(int), hipMemcpyHostToDevice, ctx->stream),
-              "set status");
-  const double* dtp = &ctx->ctr->dt;
-  for (int s = 0; s < nsteps; ++s) {
-    HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 8, ctx->stream), "reset");
-    int st = substep(ctx, P, P, ctx->Ph, 0.0, false, dtp, 0.5);
-    if (st != GRMHD_OK) return st;
-    st = substep(ctx, ctx->Ph, P, P, 0.0, true, dtp, 1.0);
-    if (st != GRMHD_OK) return st;
-    HIP_OR_FAIL(ctx, launch_ctx_dt(ctx->ctr, ctx->p.cfl, ctx->dx[0], ctx->dx[1], ctx->dx[2], ctx->stream), "dt");
-  }
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.dt, &ctx->ctr->dt, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
-              "read dt");
-  HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.status, &ctx->ctr->status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),
-              "read status");
-  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
-  *dt = host.dt;
-  if (host.status) return fail(ctx, GRMHD_ESTATE, "non-finite signal speed in the state");
-  return GRMHD_OK;
+  return run_steps(ctx, P, nullptr, 0, 0.0, nsteps, dt);
+}
+
+int grmhd_run_electrons(grmhd_ctx* ctx, double* P, double* E, int32_t nsteps, double* dt, int32_t model,
+                        double fel) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!dt) return fail(ctx, GRMHD_EINVAL, "run_electrons: NULL argument");
+  if (nsteps < 0) return fail(ctx, GRMHD_EINVAL, "run_electrons: nsteps < 0");
+  if (!(*dt > 0.0) || !std::isfinite(*dt)) return fail(ctx, GRMHD_EINVAL, "run_electrons: dt must be finite and > 0");
+  int st = electron_prep(ctx, P, E, model, fel, "run_electrons");
+  if (st != GRMHD_OK) return st;
+  return run_steps(ctx, P, E, model, fel, nsteps, dt);
 }
 
 int grmhd_fill_ghosts(grmhd_ctx* ctx, double* P, const double* base) {

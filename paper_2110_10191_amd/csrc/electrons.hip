@@ -68,7 +68,9 @@ __global__ __launch_bounds__(256) void scalar_advect_kernel(Dims d, const double
                                                             const TF* __restrict__ F1, const TF* __restrict__ F2,
                                                             const TF* __restrict__ F3, const double* __restrict__ Pb,
                                                             const double* __restrict__ Eb, const double* __restrict__ Es,
-                                                            double* __restrict__ Uk, double dt) {
+                                                            double* __restrict__ Uk, double dt,
+                                                            const double* __restrict__ dt_dev, double dt_scale) {
+  if (dt_dev) dt = dt_scale * *dt_dev;
   const TileK tk = xcd_tile_k((int)blockIdx.x, d.utx, d.uty, d.n1, d.n3);
   const int i = tk.i0 + (int)threadIdx.x;
   const int j = tk.j0 + (int)threadIdx.y;
@@ -171,24 +173,25 @@ __global__ __launch_bounds__(256) void electron_heat_kernel(Dims d, const double
 template <typename TF>
 void advect_for(int recon, const Dims& d, const Tables& t, const UpdateParams& up, const void* F1, const void* F2,
                 const void* F3, const double* Pb, const double* Eb, const double* Es, double* Uk, double dt,
-                hipStream_t s) {
+                const double* dt_dev, double dt_scale, hipStream_t s) {
   const dim3 grid(xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty)), block(d.utx, d.uty, 1);
   const TF *f1 = (const TF*)F1, *f2 = (const TF*)F2, *f3 = (const TF*)F3;
   if (recon == GRMHD_RECON_MC)
     hipLaunchKernelGGL((scalar_advect_kernel<TF, GRMHD_RECON_MC>), grid, block, 0, s, d, t.cent, up, f1, f2, f3, Pb,
-                       Eb, Es, Uk, dt);
+                       Eb, Es, Uk, dt, dt_dev, dt_scale);
   else
     hipLaunchKernelGGL((scalar_advect_kernel<TF, GRMHD_RECON_WENO5>), grid, block, 0, s, d, t.cent, up, f1, f2, f3,
-                       Pb, Eb, Es, Uk, dt);
+                       Pb, Eb, Es, Uk, dt, dt_dev, dt_scale);
 }
 
 }  // namespace
 
 hipError_t launch_scalar_advect(bool mixed, int recon, const Dims& d, const Tables& t, const UpdateParams& up,
                                 const void* F1, const void* F2, const void* F3, const double* Pb, const double* Eb,
-                                const double* Es, double* Uk, double dt, hipStream_t s) {
-  if (mixed) advect_for<float>(recon, d, t, up, F1, F2, F3, Pb, Eb, Es, Uk, dt, s);
-  else advect_for<double>(recon, d, t, up, F1, F2, F3, Pb, Eb, Es, Uk, dt, s);
+                                const double* Es, double* Uk, double dt, const double* dt_dev, double dt_scale,
+                                hipStream_t s) {
+  if (mixed) advect_for<float>(recon, d, t, up, F1, F2, F3, Pb, Eb, Es, Uk, dt, dt_dev, dt_scale, s);
+  else advect_for<double>(recon, d, t, up, F1, F2, F3, Pb, Eb, Es, Uk, dt, dt_dev, dt_scale, s);
   return hipGetLastError();
 }
 

@@ -136,12 +136,14 @@ hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, c
 // electron heating: the ghost zones of the two entropies (the primitives'
 // rules without the axis sign change and the inflow fix); the advection of
 // U_K = sqrt(-g) rho u^t K from the face mass fluxes (F of double or float);
-// the u ceiling and the heating of the new state
+// the u ceiling and the heating of the new state. The advection's step is dt,
+// or dt_scale * *dt_dev when dt_dev is not null.
 hipError_t launch_fill_scalar_ghosts(const grmhd_problem& p, const Dims& d, double* E, const double* dirichlet_src,
                                      hipStream_t s);
 hipError_t launch_scalar_advect(bool mixed, int recon, const Dims& d, const Tables& t, const UpdateParams& up,
                                 const void* F1, const void* F2, const void* F3, const double* Pb, const double* Eb,
-                                const double* Es, double* Uk, double dt, hipStream_t s);
+                                const double* Es, double* Uk, double dt, const double* dt_dev, double dt_scale,
+                                hipStream_t s);
 hipError_t launch_electron_heat(const Dims& d, const Tables& t, double gam, double* P, const double* Uk, double* E,
                                 int model, double fel, hipStream_t s);
 

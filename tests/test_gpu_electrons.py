@@ -145,3 +145,25 @@ def test_full_size_torus_sampled_slabs(lib):
         eE = rel_l1(Eg[:, k0:k0 + 1], Er)
         print("slab", k0, eP.max(), eE)
         assert eP.max() <= 1e-10 and eE.max() <= 1e-10, (k0, eP, eE)
+
+
+def test_run_electrons_equals_the_host_loop(lib):
+    """grmhd_run_electrons keeps the step size on the device and gives the
+    same bits as a host loop of dt <- min(dt_next, 1.3 dt) around
+    grmhd_step_electrons."""
+    prm, P0 = problems.fm_torus(n1=72, n2=20, n3=5)
+    E0 = problems.electron_scalars(P0, prm["gam"], te_ti=0.5)
+    sim = lib.Sim(prm)
+    Pa, Ea = sim.to_device(P0), sim.to_device(E0)
+    Pb, Eb = sim.to_device(P0), sim.to_device(E0)
+    dt0 = sim.get_dt(Pa)
+    dt = dt0
+    for _ in range(5):
+        dt = min(sim.step_electrons(Pa, Ea, dt, "howes"), 1.3 * dt)
+    dt_dev = sim.run_electrons(Pb, Eb, 5, dt0, "howes")
+    assert dt_dev == dt
+    assert np.array_equal(sim.to_host(Pa), sim.to_host(Pb))
+    assert np.array_equal(sim.to_host(Ea), sim.to_host(Eb))
+    with pytest.raises(lib.GrmhdError):
+        sim.run_electrons(Pb, Eb, 1, dt, 9)
+    sim.close()
