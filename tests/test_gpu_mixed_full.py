@@ -58,3 +58,35 @@ def test_mixed_one_step_vs_oracle_slab(lib):
     err = rel_l1(got[:, 40:41], ref)
     print("mixed vs oracle, 1 step, slab 40:", err)
     assert (err <= 1e-5).all(), err
+
+
+def _mode_error(lib, n, precision, recon, T=0.5):
+    from problems.modes import mode_solution
+    prm, P0 = problems.linear_modes(n=n, kvec=(1, 1, 0), n3=1, recon=recon, precision=precision)
+    sim = lib.Sim(prm)
+    P = sim.to_device(P0)
+    t, dt = 0.0, sim.get_dt(P)
+    while t < T - 1e-14:
+        dt = min(dt, T - t)
+        dn = sim.step(P, dt)
+        t += dt
+        dt = min(dn, 1.3 * dt)
+    out = interior(sim.to_host(P), prm)
+    sim.close()
+    return float(np.abs(out - mode_solution(prm, T)).mean())
+
+
+@pytest.mark.parametrize("recon", [problems.RECON_MC, problems.RECON_WENO5], ids=["mc", "weno5"])
+def test_modes_convergence_fp64_and_mixed(lib, recon):
+    """Linear modes (amplitude 1e-4 on an O(1) background, k = 2 pi (1, 1, 0)):
+    the FP64 path converges at second order down to n = 128; the mixed path
+    follows it while the truncation error dominates and then levels off at the
+    FP32 rounding floor, about 1e-7 of the background."""
+    ns = (16, 32, 64, 128)
+    e64 = [_mode_error(lib, n, problems.FP64, recon) for n in ns]
+    e32 = [_mode_error(lib, n, problems.MIXED, recon) for n in ns]
+    s64 = np.log2(np.array(e64[:-1]) / np.array(e64[1:]))
+    print("fp64", e64, s64, "mixed", e32)
+    assert (s64 > 1.9).all(), (e64, s64)
+    assert abs(e32[0] / e64[0] - 1.0) < 0.05, (e32, e64)
+    assert max(e32) < 1e-6 and e32[-1] < 1.5e-7, e32
