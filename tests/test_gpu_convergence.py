@@ -1,0 +1,38 @@
+"""The paper's Tests section problems on the GPU at resolutions the oracle
+cannot reach in a test: un-magnetised Bondi flow on 2D N^2 grids, whose
+deviation from the stationary Michel solution (outside r = 2.5) must fall at
+second order, as the oracle's does on its 16-64 grids."""
+
+import numpy as np
+import pytest
+
+import problems
+
+NG = 3
+pytestmark = pytest.mark.gpu
+
+
+def bondi_error(lib, n, T=5.0):
+    prm, P0 = problems.bondi(n1=n, n2=n, n3=1)
+    sim = lib.Sim(prm)
+    P = sim.to_device(P0)
+    t, dt = 0.0, sim.get_dt(P)
+    while t < T - 1e-12:
+        dt = min(dt, T - t)
+        dn = sim.step(P, dt)
+        t += dt
+        dt = min(dn, 1.3 * dt)
+    rho = sim.to_host(P)[0, NG, NG:NG + n, NG:NG + n]
+    sim.close()
+    x1 = prm["x1min"] + (np.arange(n) + 0.5) * (prm["x1max"] - prm["x1min"]) / n
+    r = np.broadcast_to(np.exp(x1), (n, n))
+    m = r > 2.5
+    return float(np.abs(rho - P0[0, NG, NG:NG + n, NG:NG + n])[m].mean())
+
+
+def test_bondi_second_order_to_256(lib):
+    ns = (32, 64, 128, 256)
+    e = [bondi_error(lib, n) for n in ns]
+    slopes = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    print("bondi L1", e, "slopes", slopes)
+    assert (slopes > 1.8).all(), (e, slopes)
