@@ -35,6 +35,7 @@ sys.path.insert(0, HERE)
 
 HBM_PEAK = 8.0e12          # bytes/s, MI355X HBM3E
 FP64_PEAK = 78.6e12        # flop/s, MI355X FP64 vector
+FP32_PEAK = 157.3e12       # flop/s, MI355X FP32 vector
 NG = 3
 
 
@@ -102,6 +103,22 @@ def measured_traffic(kernel, workload):
         if (rec.get("kernel") == kernel and rec.get("workload") == workload
                 and rec.get("library_hash") == tune.library_hash()):
             return float(rec["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def measured_flops(workload):
+    """Per-kernel FP64 and FP32 VALU flops per launch from the committed counter
+    summary (profiles/valu_flops.json: (2 FMA + ADD + MUL) x 64 lanes per
+    precision), only while the library is the build they were taken on."""
+    path = os.path.join(HERE, "profiles", "valu_flops.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        from paper_2110_10191_amd import tune
+        if rec.get("library_hash") == tune.library_hash() and workload in rec.get("workloads", {}):
+            return rec["workloads"][workload]
     except (OSError, ValueError, KeyError):
         pass
     return None
@@ -379,6 +396,17 @@ def main():
     if roofline["traffic"]:
         views["measured_frac"] = roofline["traffic"] / (ms / n / 1e3) / HBM_PEAK
         views["measured_frac_of_copy"] = roofline["traffic"] / (ms / n / 1e3) / copy_bw
+    # the VALU view: counted FP64 / FP32 flops per launch over the live mean
+    # launch time, against the vector peaks
+    flops = measured_flops(workload)
+    if flops:
+        valu = {}
+        for k, rec in flops.items():
+            if k in kernels and kernels[k][1]:
+                t = kernels[k][0] / kernels[k][1] / 1e3
+                valu[k] = {"fp64_TFLOPs": rec["fp64"] / t / 1e12, "fp64_frac": rec["fp64"] / t / FP64_PEAK,
+                           "fp32_TFLOPs": rec["fp32"] / t / 1e12, "fp32_frac": rec["fp32"] / t / FP32_PEAK}
+        views["valu"] = valu
     roofline["views"] = views
 
     if args.electrons:
