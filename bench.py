@@ -264,7 +264,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build runs the zone update on a single device "
+        print("bench.py measures one GPU: the library runs the zone update on a single device "
               "(multi-GPU block decomposition is a design note only). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
