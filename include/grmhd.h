@@ -272,6 +272,17 @@ GRMHD_API int grmhd_batch_get(grmhd_batch *b, double *dt, int32_t *status);
  * from the previous call the job table is re-uploaded and the step graph
  * re-captured (synchronises once); otherwise asynchronous. */
 GRMHD_API int grmhd_batch_step(grmhd_batch *b, double *const *P, const int32_t *active, int32_t nsteps);
+/* As grmhd_batch_step, with electron heating (as grmhd_step_electrons) for
+ * every active job j with E[j] != NULL, with its own heating model model[j]
+ * and constant fraction fel[j] (host arrays of n; entries of jobs without
+ * entropies are ignored). A job's evolution (P and E) is the same as a loop of
+ * grmhd_step_electrons (or grmhd_step, without E) on its own context with
+ * dt <- min(dt_next, 1.3 dt). The first call with entropies for a context
+ * allocates its electron scratch. A change of any E[j], model[j] or fel[j]
+ * re-captures the step graph. Errors: as grmhd_batch_step; EINVAL for an
+ * unknown model or fel outside [0, 1]; ENOMEM. */
+GRMHD_API int grmhd_batch_step_electrons(grmhd_batch *b, double *const *P, double *const *E, const int32_t *model,
+                                         const double *fel, const int32_t *active, int32_t nsteps);
 /* Kernel timing of batch steps, as grmhd_profile / grmhd_profile_read for a
  * context (same kernel classes, each launch spanning every active job). While
  * profiling is on, grmhd_batch_step enqueues its launches directly, each

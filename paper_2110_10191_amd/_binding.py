@@ -16,7 +16,7 @@ EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
     "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_speeds", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
-    "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step",
+    "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step", "grmhd_batch_step_electrons",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
 ]
 KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5, "electrons": 6}
@@ -100,6 +100,8 @@ def _load():
         "grmhd_batch_set_dt": ([vp, dp], ctypes.c_int),
         "grmhd_batch_get": ([vp, dp, ctypes.POINTER(i32)], ctypes.c_int),
         "grmhd_batch_step": ([vp, ctypes.POINTER(vp), ctypes.POINTER(i32), i32], ctypes.c_int),
+        "grmhd_batch_step_electrons": ([vp, ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(i32),
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i32), i32], ctypes.c_int),
         "grmhd_batch_free": ([vp], ctypes.c_int),
         "grmhd_batch_profile": ([vp, i32], ctypes.c_int),
         "grmhd_batch_profile_read": ([vp, i32, dp, ctypes.POINTER(i64)], ctypes.c_int),
@@ -314,6 +316,18 @@ def grmhd_batch_step(b, states, active=None, nsteps=1):
     _bcheck(lib.grmhd_batch_step(b, ptrs, act, int(nsteps)), b)
 
 
+def grmhd_batch_step_electrons(b, states, electrons, active=None, nsteps=1):
+    """electrons: per job None (no electron heating) or (E, model, fel)."""
+    n = len(states)
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(s) if s is not None else None for s in states])
+    eptr = (ctypes.c_void_p * n)(*[_ptr(e[0]) if e is not None else None for e in electrons])
+    models = (ctypes.c_int32 * n)(*[(HEAT_MODELS[e[1]] if isinstance(e[1], str) else int(e[1])) if e is not None
+                                    else 0 for e in electrons])
+    fels = (ctypes.c_double * n)(*[float(e[2]) if e is not None else 0.0 for e in electrons])
+    act = None if active is None else (ctypes.c_int32 * n)(*[1 if a else 0 for a in active])
+    _bcheck(lib.grmhd_batch_step_electrons(b, ptrs, eptr, models, fels, act, int(nsteps)), b)
+
+
 def grmhd_batch_profile(b, enable):
     _bcheck(lib.grmhd_batch_profile(b, 1 if enable else 0), b)
 
@@ -348,8 +362,12 @@ class Batch:
     def get(self):
         return grmhd_batch_get(self.b, len(self.sims))
 
-    def step(self, states, active=None, nsteps=1):
-        grmhd_batch_step(self.b, states, active, nsteps)
+    def step(self, states, active=None, nsteps=1, electrons=None):
+        """electrons: None, or per job None / (E, model, fel) for electron heating."""
+        if electrons is None:
+            grmhd_batch_step(self.b, states, active, nsteps)
+        else:
+            grmhd_batch_step_electrons(self.b, states, electrons, active, nsteps)
 
     def profile(self, enable):
         grmhd_batch_profile(self.b, enable)

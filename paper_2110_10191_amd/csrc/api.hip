@@ -198,21 +198,10 @@ int read_dt(grmhd_ctx* c, double* dt) {
 int electron_prep(grmhd_ctx* ctx, const double* P, const double* E, int32_t model, double fel, const char* who) {
   std::string w(who);
   if (!P || !E) return fail(ctx, GRMHD_EINVAL, w + ": NULL state");
-  if (model < GRMHD_HEAT_CONSTANT || model > GRMHD_HEAT_SHARMA)
-    return fail(ctx, GRMHD_EINVAL, w + ": unknown heating model");
-  if (model == GRMHD_HEAT_CONSTANT && !(fel >= 0.0 && fel <= 1.0))
-    return fail(ctx, GRMHD_EINVAL, w + ": fel must lie in [0, 1]");
-  if (!ctx->Eh) {
-    const size_t bytes = (size_t)GRMHD_NSCALAR * ctx->d.sv * sizeof(double);
-    if (dalloc(&ctx->Eh, bytes) != hipSuccess || dalloc(&ctx->Uk, bytes) != hipSuccess) {
-      if (ctx->Eh) (void)hipFree(ctx->Eh);
-      if (ctx->Uk) (void)hipFree(ctx->Uk);
-      ctx->Eh = ctx->Uk = nullptr;
-      return fail(ctx, GRMHD_ENOMEM, w + ": scratch allocation failed");
-    }
-    // ghost and padding zones of the half-step entropies that no rule writes stay finite
-    HIP_OR_FAIL(ctx, hipMemsetAsync(ctx->Eh, 0, bytes, ctx->stream), "clear scratch");
-  }
+  if (!heat_args_ok(model, fel)) return fail(ctx, GRMHD_EINVAL, w + ": unknown heating model or fel outside [0, 1]");
+  const hipError_t e = ctx_electron_scratch(ctx);
+  if (e == hipErrorOutOfMemory) return fail(ctx, GRMHD_ENOMEM, w + ": scratch allocation failed");
+  HIP_OR_FAIL(ctx, e, "electron scratch");
   return GRMHD_OK;
 }
 
@@ -249,6 +238,26 @@ int run_steps(grmhd_ctx* ctx, double* P, double* E, int32_t model, double fel, i
 }
 
 }  // namespace
+
+bool heat_args_ok(int32_t model, double fel) {
+  if (model < GRMHD_HEAT_CONSTANT || model > GRMHD_HEAT_SHARMA) return false;
+  return model != GRMHD_HEAT_CONSTANT || (fel >= 0.0 && fel <= 1.0);
+}
+
+hipError_t ctx_electron_scratch(grmhd_ctx* c) {
+  if (c->Eh) return hipSuccess;
+  const size_t bytes = (size_t)GRMHD_NSCALAR * c->d.sv * sizeof(double);
+  hipError_t e = hipMalloc((void**)&c->Eh, bytes);
+  if (e == hipSuccess) e = hipMalloc((void**)&c->Uk, bytes);
+  // ghost and padding zones of the half-step entropies that no rule writes stay finite
+  if (e == hipSuccess) e = hipMemsetAsync(c->Eh, 0, bytes, c->stream);
+  if (e != hipSuccess) {
+    if (c->Eh) (void)hipFree(c->Eh);
+    if (c->Uk) (void)hipFree(c->Uk);
+    c->Eh = c->Uk = nullptr;
+  }
+  return e;
+}
 
 extern "C" {
 

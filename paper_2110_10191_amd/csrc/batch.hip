@@ -6,6 +6,9 @@
 //   predictor: ghosts(P); reset(fail); sweeps(P); update(P -> P_h, dt/2); fixup
 //   corrector: ghosts(P_h); reset(ctop, fail); sweeps(P_h) + ctop; update((P, P_h) -> P, dt); fixup
 //   dt_j <- min(cfl / sum_d (ctop_d / dx_d), 1.3 dt_j)
+// With electron heating (jobs given entropies E), each substep also fills
+// the scalar ghosts after the fluid ghosts, advects the entropies after the
+// sweeps and heats after the fixup, as a context's electron step does.
 // Every job reads only its own dt, counters and arrays, so its evolution is
 // the same alone or in any mix.
 #include <cstring>
@@ -28,6 +31,10 @@ struct grmhd_batch {
   // configuration the current graph was captured for
   std::vector<double*> cur_P;
   std::vector<int32_t> cur_active;
+  std::vector<double*> cur_E;      // electron entropies per job (null: none)
+  std::vector<int32_t> cur_model;
+  std::vector<double> cur_fel;
+  bool electrons = false;          // some active job has entropies
   int totals[PH_COUNT] = {0};
   int nactive = 0;
   int stx = TILE_X, sty = SWEEP_TILE_Y, utx = TILE_X, uty = TILE_Y;  // tiles of every job
@@ -72,11 +79,20 @@ hipError_t enqueue_step(grmhd_batch* b) {
       ProfScope ps(b->prof, s, GRMHD_K_GHOSTS);
       if ((e = launch_batch_ghosts(bv, b->totals, corr == 1, s)) != hipSuccess) return e;
     }
+    if (b->electrons) {
+      ProfScope ps(b->prof, s, GRMHD_K_ELECTRONS);
+      if ((e = launch_batch_electrons(bv, b->totals, b->mixed, b->recon, corr == 1, 1, s)) != hipSuccess) return e;
+    }
     if ((e = launch_batch_reset(bv, corr ? (1 | 4) : 4, s)) != hipSuccess) return e;
     for (int dir = 1; dir <= 3; ++dir) {
       ProfScope ps(b->prof, s, GRMHD_K_SWEEP1 + dir - 1);
       if ((e = launch_batch_sweeps(bv, b->totals, b->recon, b->mixed, corr == 1, corr == 1, dir, s)) != hipSuccess)
         return e;
+    }
+    if (b->electrons) {
+      // before the update: in the corrector it overwrites the base state
+      ProfScope ps(b->prof, s, GRMHD_K_ELECTRONS);
+      if ((e = launch_batch_electrons(bv, b->totals, b->mixed, b->recon, corr == 1, 2, s)) != hipSuccess) return e;
     }
     {
       ProfScope ps(b->prof, s, GRMHD_K_UPDATE);
@@ -86,18 +102,37 @@ hipError_t enqueue_step(grmhd_batch* b) {
       ProfScope ps(b->prof, s, GRMHD_K_FIXUP);
       if ((e = launch_batch_update(bv, b->totals, b->mixed, corr == 1, 2, s)) != hipSuccess) return e;
     }
+    if (b->electrons) {
+      ProfScope ps(b->prof, s, GRMHD_K_ELECTRONS);
+      if ((e = launch_batch_electrons(bv, b->totals, b->mixed, b->recon, corr == 1, 3, s)) != hipSuccess) return e;
+    }
   }
   return launch_batch_dt(bv, s);
 }
 
-int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
+// E, model, fel: electron heating per job (E null, or E[j] null: none)
+int configure(grmhd_batch* b, double* const* P, double* const* E, const int32_t* model, const double* fel,
+              const int32_t* active) {
   const int n = (int)b->ctx.size();
   std::vector<JobDesc> jobs;
   std::vector<int> counts;  // [job][phase]
+  bool electrons = false;
   for (int j = 0; j < n; ++j) {
     if (active && !active[j]) continue;
     if (!P[j]) return bfail(b, GRMHD_EINVAL, "batch_step: NULL state for an active job");
-    const grmhd_ctx* c = b->ctx[j];
+    grmhd_ctx* c = b->ctx[j];
+    const bool ej = E && E[j];
+    if (ej) {
+      if (!heat_args_ok(model[j], fel[j]))
+        return bfail(b, GRMHD_EINVAL, "batch_step_electrons: unknown heating model or fel outside [0, 1]");
+      const hipError_t e = ctx_electron_scratch(c);
+      if (e != hipSuccess)
+        return bfail(b, e == hipErrorOutOfMemory ? GRMHD_ENOMEM : GRMHD_EDEVICE,
+                     std::string("electron scratch: ") + hipGetErrorString(e));
+      // the scratch is cleared on the context's stream
+      BHIP(b, hipStreamSynchronize(c->stream), "synchronize");
+      electrons = true;
+    }
     JobDesc jd;
     std::memset(&jd, 0, sizeof(jd));
     jd.p = c->p;
@@ -117,6 +152,13 @@ int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
     jd.ctr = c->ctr;
     jd.dt = b->d_dt + j;
     jd.status = b->d_status + j;
+    if (ej) {
+      jd.E = E[j];
+      jd.Eh = c->Eh;
+      jd.Uk = c->Uk;
+      jd.heat_model = model[j];
+      jd.fel = fel[j];
+    }
     jobs.push_back(jd);
     int cnt[PH_COUNT];
     job_phase_blocks(jd.d, cnt);
@@ -140,6 +182,17 @@ int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
   b->cur_P.assign(P, P + n);
   b->cur_active.assign(n, 1);
   if (active) b->cur_active.assign(active, active + n);
+  b->cur_E.assign(n, nullptr);
+  b->cur_model.assign(n, 0);
+  b->cur_fel.assign(n, 0.0);
+  if (E)
+    for (int j = 0; j < n; ++j)
+      if (E[j]) {
+        b->cur_E[j] = E[j];
+        b->cur_model[j] = model[j];
+        b->cur_fel[j] = fel[j];
+      }
+  b->electrons = electrons;
   if (na == 0) return GRMHD_OK;
   BHIP(b, hipMemcpy(b->d_jobs, jobs.data(), sizeof(JobDesc) * na, hipMemcpyHostToDevice), "upload jobs");
   BHIP(b, hipMemcpy(b->d_offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice), "upload offsets");
@@ -159,15 +212,38 @@ int configure(grmhd_batch* b, double* const* P, const int32_t* active) {
   return GRMHD_OK;
 }
 
-bool same_config(const grmhd_batch* b, double* const* P, const int32_t* active) {
+bool same_config(const grmhd_batch* b, double* const* P, double* const* E, const int32_t* model, const double* fel,
+                 const int32_t* active) {
   const size_t n = b->ctx.size();
   if (b->cur_P.size() != n) return false;
   for (size_t j = 0; j < n; ++j) {
     const int32_t a = active ? (active[j] != 0) : 1;
     if (a != (b->cur_active[j] != 0)) return false;
-    if (a && b->cur_P[j] != P[j]) return false;
+    if (!a) continue;
+    if (b->cur_P[j] != P[j]) return false;
+    double* ej = E ? E[j] : nullptr;
+    if (b->cur_E[j] != ej) return false;
+    if (ej && (b->cur_model[j] != model[j] || b->cur_fel[j] != fel[j])) return false;
   }
   return true;
+}
+
+int batch_step(grmhd_batch* b, double* const* P, double* const* E, const int32_t* model, const double* fel,
+               const int32_t* active, int32_t nsteps) {
+  if (!P) return bfail(b, GRMHD_EINVAL, "batch_step: NULL state list");
+  if (nsteps < 0) return bfail(b, GRMHD_EINVAL, "batch_step: nsteps < 0");
+  if (!b->dt_set) return bfail(b, GRMHD_EINVAL, "batch_step: call grmhd_batch_set_dt first");
+  if (!b->exec || !same_config(b, P, E, model, fel, active)) {
+    const int st = configure(b, P, E, model, fel, active);
+    if (st != GRMHD_OK) return st;
+  }
+  if (b->nactive == 0) return GRMHD_OK;
+  if (b->prof.on) {
+    for (int s = 0; s < nsteps; ++s) BHIP(b, enqueue_step(b), "step");
+    return GRMHD_OK;
+  }
+  for (int s = 0; s < nsteps; ++s) BHIP(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
+  return GRMHD_OK;
 }
 
 }  // namespace
@@ -239,20 +315,14 @@ int grmhd_batch_get(grmhd_batch* b, double* dt, int32_t* status) {
 
 int grmhd_batch_step(grmhd_batch* b, double* const* P, const int32_t* active, int32_t nsteps) {
   if (!b) return GRMHD_EINVAL;
-  if (!P) return bfail(b, GRMHD_EINVAL, "batch_step: NULL state list");
-  if (nsteps < 0) return bfail(b, GRMHD_EINVAL, "batch_step: nsteps < 0");
-  if (!b->dt_set) return bfail(b, GRMHD_EINVAL, "batch_step: call grmhd_batch_set_dt first");
-  if (!b->exec || !same_config(b, P, active)) {
-    const int st = configure(b, P, active);
-    if (st != GRMHD_OK) return st;
-  }
-  if (b->nactive == 0) return GRMHD_OK;
-  if (b->prof.on) {
-    for (int s = 0; s < nsteps; ++s) BHIP(b, enqueue_step(b), "step");
-    return GRMHD_OK;
-  }
-  for (int s = 0; s < nsteps; ++s) BHIP(b, hipGraphLaunch(b->exec, b->stream), "graph launch");
-  return GRMHD_OK;
+  return batch_step(b, P, nullptr, nullptr, nullptr, active, nsteps);
+}
+
+int grmhd_batch_step_electrons(grmhd_batch* b, double* const* P, double* const* E, const int32_t* model,
+                               const double* fel, const int32_t* active, int32_t nsteps) {
+  if (!b) return GRMHD_EINVAL;
+  if (!E || !model || !fel) return bfail(b, GRMHD_EINVAL, "batch_step_electrons: NULL list");
+  return batch_step(b, P, E, model, fel, active, nsteps);
 }
 
 int grmhd_batch_profile(grmhd_batch* b, int32_t enable) {

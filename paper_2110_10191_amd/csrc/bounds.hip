@@ -157,6 +157,22 @@ __global__ __launch_bounds__(256) void ghost_batch_kernel(BatchView bv, int corr
   else ghost_x3_body(J.p, J.d, tgt, src, b);
 }
 
+// the electron entropies of the jobs that have them: predictor fills E,
+// corrector E_h (Dirichlet ghosts from E)
+template <int DIR>
+__global__ __launch_bounds__(256) void scalar_ghost_batch_kernel(BatchView bv, int corrector) {
+  const int* offs = bv.offs + (PH_GHOST1 + DIR - 1) * (bv.njobs + 1);
+  const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
+  const JobDesc& J = bv.jobs[jb];
+  if (!J.E) return;
+  const int b = (int)blockIdx.x - offs[jb];
+  double* tgt = global_ptr(corrector ? J.Eh : J.E);
+  const double* src = global_ptr(J.E);
+  if (DIR == 1) ghost_x1_body<GRMHD_NSCALAR, true>(J.p, J.d, nullptr, tgt, src, b * (int)blockDim.x + (int)threadIdx.x);
+  else if (DIR == 2) ghost_x2_body<GRMHD_NSCALAR, true>(J.p, J.d, tgt, src, b);
+  else ghost_x3_body<GRMHD_NSCALAR, true>(J.p, J.d, tgt, src, b);
+}
+
 // corner-centred divergence of sqrt(-g) B; corner (i, j, k) sits at (i-1/2, j-1/2, k-1/2)
 __global__ void divb_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
                             const double* __restrict__ P, unsigned long long* out) {
@@ -285,6 +301,13 @@ hipError_t launch_batch_ghosts(const BatchView& bv, const int* totals, bool corr
   hipLaunchKernelGGL(ghost_batch_kernel<1>, dim3(totals[PH_GHOST1]), dim3(256), 0, s, bv, corrector ? 1 : 0);
   hipLaunchKernelGGL(ghost_batch_kernel<2>, dim3(totals[PH_GHOST2]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
   hipLaunchKernelGGL(ghost_batch_kernel<3>, dim3(totals[PH_GHOST3]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_scalar_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s) {
+  hipLaunchKernelGGL(scalar_ghost_batch_kernel<1>, dim3(totals[PH_GHOST1]), dim3(256), 0, s, bv, corrector ? 1 : 0);
+  hipLaunchKernelGGL(scalar_ghost_batch_kernel<2>, dim3(totals[PH_GHOST2]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
+  hipLaunchKernelGGL(scalar_ghost_batch_kernel<3>, dim3(totals[PH_GHOST3]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
   return hipGetLastError();
 }
 

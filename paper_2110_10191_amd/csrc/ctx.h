@@ -101,3 +101,9 @@ struct grmhd_ctx {
   std::string err;
 };
 
+// electron heating helpers shared by the context and batch calls: the model /
+// fel check, and the context's scratch (half-step entropies and U_K),
+// allocated and its half-step array cleared on first use
+bool heat_args_ok(int32_t model, double fel);
+hipError_t ctx_electron_scratch(grmhd_ctx* c);
+

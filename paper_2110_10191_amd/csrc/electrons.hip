@@ -63,15 +63,13 @@ __device__ inline void scalar_flux(const double* E, int sv, int c, int st, doubl
   }
 }
 
+// b: block index within this job's grid (the update tile, XCD-aware order)
 template <typename TF, int RECON>
-__global__ __launch_bounds__(256) void scalar_advect_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
-                                                            const TF* __restrict__ F1, const TF* __restrict__ F2,
-                                                            const TF* __restrict__ F3, const double* __restrict__ Pb,
-                                                            const double* __restrict__ Eb, const double* __restrict__ Es,
-                                                            double* __restrict__ Uk, double dt,
-                                                            const double* __restrict__ dt_dev, double dt_scale) {
-  if (dt_dev) dt = dt_scale * *dt_dev;
-  const TileK tk = xcd_tile_k((int)blockIdx.x, d.utx, d.uty, d.n1, d.n3);
+__device__ void scalar_advect_body(const Dims& d, const double* __restrict__ cent, const UpdateParams& up,
+                                   const TF* __restrict__ F1, const TF* __restrict__ F2, const TF* __restrict__ F3,
+                                   const double* __restrict__ Pb, const double* __restrict__ Eb,
+                                   const double* __restrict__ Es, double* __restrict__ Uk, double dt, int b) {
+  const TileK tk = xcd_tile_k(b, d.utx, d.uty, d.n1, d.n3);
   const int i = tk.i0 + (int)threadIdx.x;
   const int j = tk.j0 + (int)threadIdx.y;
   if (!tk.valid || i >= d.n1 || j >= d.n2) return;
@@ -102,6 +100,32 @@ __global__ __launch_bounds__(256) void scalar_advect_kernel(Dims d, const double
   const double D = gdet * Pb[c] * ut;
 #pragma unroll
   for (int s = 0; s < GRMHD_NSCALAR; ++s) Uk[s * d.sv + c] = D * Eb[s * d.sv + c] - dt * div[s];
+}
+
+template <typename TF, int RECON>
+__global__ __launch_bounds__(256) void scalar_advect_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
+                                                            const TF* __restrict__ F1, const TF* __restrict__ F2,
+                                                            const TF* __restrict__ F3, const double* __restrict__ Pb,
+                                                            const double* __restrict__ Eb, const double* __restrict__ Es,
+                                                            double* __restrict__ Uk, double dt,
+                                                            const double* __restrict__ dt_dev, double dt_scale) {
+  if (dt_dev) dt = dt_scale * *dt_dev;
+  scalar_advect_body<TF, RECON>(d, cent, up, F1, F2, F3, Pb, Eb, Es, Uk, dt, (int)blockIdx.x);
+}
+
+// every job with entropies in one grid: predictor (E -> U_K, base P), corrector
+// (E_h fluxes, base E and P)
+template <typename TF, int RECON>
+__global__ __launch_bounds__(256) void scalar_advect_batch_kernel(BatchView bv, int corrector) {
+  const int* offs = bv.offs + PH_UPDATE * (bv.njobs + 1);
+  const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
+  const JobDesc& J = bv.jobs[jb];
+  if (!J.E) return;
+  const double dt = corrector ? *J.dt : 0.5 * *J.dt;
+  scalar_advect_body<TF, RECON>(J.d, global_ptr(J.t.cent), J.up, global_ptr((const TF*)J.F[0]),
+                                global_ptr((const TF*)J.F[1]), global_ptr((const TF*)J.F[2]), global_ptr(J.P),
+                                global_ptr(J.E), global_ptr(corrector ? J.Eh : J.E), global_ptr(J.Uk), dt,
+                                (int)blockIdx.x - offs[jb]);
 }
 
 __device__ double heating_fraction(int model, double fel, double rho, double u, double kel, double bsq, double gam) {
@@ -137,10 +161,11 @@ __device__ double heating_fraction(int model, double fel, double rho, double u, 
   return 1.0 / (1.0 + qi_qe);
 }
 
-__global__ __launch_bounds__(256) void electron_heat_kernel(Dims d, const double* __restrict__ cent, double gam,
-                                                            double* __restrict__ P, const double* __restrict__ Uk,
-                                                            double* __restrict__ E, int model, double fel) {
-  const TileK tk = xcd_tile_k((int)blockIdx.x, d.utx, d.uty, d.n1, d.n3);
+// b: block index within this job's grid
+__device__ void electron_heat_body(const Dims& d, const double* __restrict__ cent, double gam, double* __restrict__ P,
+                                   const double* __restrict__ Uk, double* __restrict__ E, int model, double fel,
+                                   int b) {
+  const TileK tk = xcd_tile_k(b, d.utx, d.uty, d.n1, d.n3);
   const int i = tk.i0 + (int)threadIdx.x;
   const int j = tk.j0 + (int)threadIdx.y;
   if (!tk.valid || i >= d.n1 || j >= d.n2) return;
@@ -170,6 +195,22 @@ __global__ __launch_bounds__(256) void electron_heat_kernel(Dims d, const double
   E[d.sv + c] = kel;
 }
 
+__global__ __launch_bounds__(256) void electron_heat_kernel(Dims d, const double* __restrict__ cent, double gam,
+                                                            double* __restrict__ P, const double* __restrict__ Uk,
+                                                            double* __restrict__ E, int model, double fel) {
+  electron_heat_body(d, cent, gam, P, Uk, E, model, fel, (int)blockIdx.x);
+}
+
+// predictor: heats P_h into E_h; corrector: P into E
+__global__ __launch_bounds__(256) void electron_heat_batch_kernel(BatchView bv, int corrector) {
+  const int* offs = bv.offs + PH_UPDATE * (bv.njobs + 1);
+  const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
+  const JobDesc& J = bv.jobs[jb];
+  if (!J.E) return;
+  electron_heat_body(J.d, global_ptr(J.t.cent), J.p.gam, global_ptr(corrector ? J.P : J.Ph), global_ptr(J.Uk),
+                     global_ptr(corrector ? J.E : J.Eh), J.heat_model, J.fel, (int)blockIdx.x - offs[jb]);
+}
+
 template <typename TF>
 void advect_for(int recon, const Dims& d, const Tables& t, const UpdateParams& up, const void* F1, const void* F2,
                 const void* F3, const double* Pb, const double* Eb, const double* Es, double* Uk, double dt,
@@ -192,6 +233,25 @@ hipError_t launch_scalar_advect(bool mixed, int recon, const Dims& d, const Tabl
                                 hipStream_t s) {
   if (mixed) advect_for<float>(recon, d, t, up, F1, F2, F3, Pb, Eb, Es, Uk, dt, dt_dev, dt_scale, s);
   else advect_for<double>(recon, d, t, up, F1, F2, F3, Pb, Eb, Es, Uk, dt, dt_dev, dt_scale, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_electrons(const BatchView& bv, const int* totals, bool mixed, int recon, bool corrector,
+                                  int which, hipStream_t s) {
+  if (which == 1) return launch_batch_scalar_ghosts(bv, totals, corrector, s);
+  const dim3 grid(totals[PH_UPDATE]), block(bv.utx, bv.uty, 1);
+  const int c = corrector ? 1 : 0;
+  if (which == 2) {
+    if (mixed) {
+      if (recon == GRMHD_RECON_MC) hipLaunchKernelGGL((scalar_advect_batch_kernel<float, GRMHD_RECON_MC>), grid, block, 0, s, bv, c);
+      else hipLaunchKernelGGL((scalar_advect_batch_kernel<float, GRMHD_RECON_WENO5>), grid, block, 0, s, bv, c);
+    } else {
+      if (recon == GRMHD_RECON_MC) hipLaunchKernelGGL((scalar_advect_batch_kernel<double, GRMHD_RECON_MC>), grid, block, 0, s, bv, c);
+      else hipLaunchKernelGGL((scalar_advect_batch_kernel<double, GRMHD_RECON_WENO5>), grid, block, 0, s, bv, c);
+    }
+  } else {
+    hipLaunchKernelGGL(electron_heat_batch_kernel, grid, block, 0, s, bv, c);
+  }
   return hipGetLastError();
 }
 

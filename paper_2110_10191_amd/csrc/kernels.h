@@ -51,6 +51,12 @@ struct JobDesc {
   Counters* ctr;
   double* dt;       // device scalar: the job's step size for the next step
   int* status;      // device scalar: set to 1 when a non-finite speed appears
+  // electron heating (E null: the job has none)
+  double* E;        // the job's entropies (caller-owned)
+  double* Eh;       // half-step entropies
+  double* Uk;       // advected sqrt(-g) rho u^t K of the current substep
+  int heat_model;
+  double fel;
 };
 
 enum { PH_GHOST1 = 0, PH_GHOST2, PH_GHOST3, PH_SWEEP1, PH_SWEEP2, PH_SWEEP3, PH_UPDATE, PH_COUNT };
@@ -98,6 +104,12 @@ hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon
 hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, int which,
                                hipStream_t s);
 hipError_t launch_batch_reset(const BatchView& bv, int mask, hipStream_t s);
+// electron passes of the jobs that have entropies (the others' blocks return
+// at once): which 1 the scalar ghosts (ghost phase grids), 2 the advection, 3
+// the heating (update phase grid)
+hipError_t launch_batch_electrons(const BatchView& bv, const int* totals, bool mixed, int recon, bool corrector,
+                                  int which, hipStream_t s);
+hipError_t launch_batch_scalar_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s);
 // dt <- min(cfl / sum_d(ctop_d / dx_d), 1.3 dt) per job, on the device
 hipError_t launch_batch_dt(const BatchView& bv, hipStream_t s);
 

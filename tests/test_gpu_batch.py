@@ -219,3 +219,48 @@ def test_a_non_finite_state_is_an_error_of_the_step(lib):
         sim.get_dt(P)
     assert e.value.status == lib.GRMHD_ESTATE
     sim.close()
+
+
+def test_batch_with_electrons_equals_each_job_alone(lib):
+    """Electron heating in the batch: jobs with and without entropies, with
+    different heating models, share every grid; each job's primitives,
+    entropies and step size equal, bit for bit, a host loop of
+    grmhd_step_electrons (or grmhd_step) on its own context."""
+    jobs = [problems.fm_torus(n1=48, n2=28, n3=4), problems.bondi(n1=40, n2=24, n3=2, a=0.7),
+            problems.linear_modes(n=12, n3=9, kvec=(1, 1, 0))]
+    heat = [("howes", 0.0), None, ("constant", 0.3)]
+    nsteps = 4
+    alone = []
+    for (prm, P0), h in zip(jobs, heat):
+        sim = lib.Sim(prm)
+        P = sim.to_device(P0)
+        E = sim.to_device(problems.electron_scalars(P0, prm["gam"], te_ti=0.5)) if h else None
+        dt = sim.get_dt(P)
+        for _ in range(nsteps):
+            dn = sim.step_electrons(P, E, dt, *h) if h else sim.step(P, dt)
+            dt = min(dn, 1.3 * dt)
+        alone.append((sim.to_host(P), sim.to_host(E) if h else None, dt))
+        sim.close()
+    sims = [lib.Sim(prm) for prm, _ in jobs]
+    states = [s.to_device(P0) for s, (_, P0) in zip(sims, jobs)]
+    ents = [s.to_device(problems.electron_scalars(P0, prm["gam"], te_ti=0.5)) if h else None
+            for s, (prm, P0), h in zip(sims, jobs, heat)]
+    dt0 = [s.get_dt(P) for s, P in zip(sims, states)]
+    b = lib.Batch(sims)
+    b.set_dt(dt0)
+    electrons = [(E, h[0], h[1]) if h else None for E, h in zip(ents, heat)]
+    b.step(states, nsteps=2, electrons=electrons)
+    b.step(states, nsteps=nsteps - 2, electrons=electrons)      # replays the captured graph
+    dts, status = b.get()
+    assert status == [0, 0, 0]
+    for j, (s, P, E) in enumerate(zip(sims, states, ents)):
+        Pa, Ea, dta = alone[j]
+        assert np.array_equal(s.to_host(P), Pa), j
+        if E is not None:
+            assert np.array_equal(s.to_host(E), Ea), j
+        assert dts[j] == dta, j
+    with pytest.raises(lib.GrmhdError):
+        b.step(states, nsteps=1, electrons=[(ents[0], 9, 0.0), None, None])
+    b.close()
+    for s in sims:
+        s.close()
