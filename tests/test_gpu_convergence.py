@@ -36,3 +36,30 @@ def test_bondi_second_order_to_256(lib):
     slopes = np.log2(np.array(e[:-1]) / np.array(e[1:]))
     print("bondi L1", e, "slopes", slopes)
     assert (slopes > 1.8).all(), (e, slopes)
+
+
+def torus_drift(lib, n, T):
+    prm, P0 = problems.fm_torus(n1=n, n2=n, n3=1, noise=0.0, beta=float("inf"))
+    sim = lib.Sim(prm)
+    P = sim.to_device(P0)
+    t, dt = 0.0, sim.get_dt(P)
+    while t < T - 1e-12:
+        dt = min(dt, T - t)
+        dn = sim.step(P, dt)
+        t += dt
+        dt = min(dn, 1.3 * dt)
+    r1 = sim.to_host(P)[0, NG, NG:NG + n, NG:NG + n]
+    sim.close()
+    r0 = P0[0, NG, NG:NG + n, NG:NG + n]
+    body = r0 > 0.1
+    return float(np.abs(r1 - r0)[body].mean() / r0[body].mean())
+
+
+def test_unmagnetised_torus_stationary_to_256(lib):
+    """The Fishbone-Moncrief equilibrium without field or noise, to t = 20 M:
+    the drift of the torus body falls at second order from 64^2 to 256^2."""
+    ns = (64, 128, 256)
+    d = [torus_drift(lib, n, 20.0) for n in ns]
+    slopes = np.log2(np.array(d[:-1]) / np.array(d[1:]))
+    print("torus drift", d, "slopes", slopes)
+    assert d[-1] < 1e-3 and (slopes > 1.6).all(), (d, slopes)

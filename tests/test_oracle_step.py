@@ -181,6 +181,31 @@ def test_torus_initial_data_pins():
     assert np.allclose((P0[1] / P0[0])[body], ratio[body], rtol=1e-12)
 
 
+def _torus_body_drift(n, T):
+    """Relative L1 change of rho in the body of an unmagnetised, unperturbed
+    Fishbone-Moncrief torus (rho > 0.1) after time T, on an n x n x 1 grid."""
+    prm, P0 = problems.fm_torus(n1=n, n2=n, n3=1, noise=0.0, beta=float("inf"))
+    assert np.abs(P0[5:]).max() == 0.0
+    g = oracle.Grid(prm)
+    P, t, dt = P0.copy(), 0.0, oracle.get_dt(P0, g)
+    while t < T - 1e-12:
+        dt = min(dt, T - t)
+        P, dn, _ = oracle.step(P, g, dt)
+        t += dt
+        dt = min(dn, 1.3 * dt)
+    r0 = P0[0, NG, NG:NG + n, NG:NG + n]
+    r1 = P[0, NG, NG:NG + n, NG:NG + n]
+    body = r0 > 0.1
+    return np.abs(r1 - r0)[body].mean() / r0[body].mean()
+
+
+def test_unmagnetised_torus_is_stationary():
+    # the Fishbone-Moncrief torus is an equilibrium: without field and noise
+    # its body drifts only by the truncation error, which falls at second order
+    d = [_torus_body_drift(n, 3.0) for n in (32, 64)]
+    assert d[1] < 2e-3 and np.log2(d[0] / d[1]) > 1.7, d
+
+
 def test_floors_idempotent_monotone_and_noop_on_box():
     prm, P = problems.fm_torus(n1=32, n2=24, n3=2)
     g = oracle.Grid(prm)
