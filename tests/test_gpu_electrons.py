@@ -167,3 +167,20 @@ def test_run_electrons_equals_the_host_loop(lib):
     with pytest.raises(lib.GrmhdError):
         sim.run_electrons(Pb, Eb, 1, dt, 9)
     sim.close()
+
+
+@pytest.mark.parametrize("make,model,fel", [
+    (lambda: problems.linear_modes(n=67, n3=2, amp=1e-3), el.MODEL_SHARMA, 0.0),     # ragged tiles, thin x3
+    (lambda: problems.linear_modes(n=64, n3=1, amp=1e-3), el.MODEL_CONSTANT, 1.0),   # exact tiles, one plane
+    (lambda: problems.fm_torus(n1=48, n2=3, n3=2), el.MODEL_KAWAZURA, 0.0),          # smallest polar grid
+    (lambda: problems.fm_torus(n1=130, n2=9, n3=3, recon=problems.RECON_WENO5), el.MODEL_ROWAN, 0.0),
+], ids=["ragged", "one_plane", "polar_n2_3", "weno5_ragged"])
+def test_electron_edge_shapes(lib, make, model, fel):
+    prm, P0 = make()
+    E0 = problems.electron_scalars(P0, prm["gam"], te_ti=0.5)
+    Pr, Er, dts, _ = oracle_run(prm, P0, E0, 3, model, fel)
+    Pg, Eg, _ = gpu_run(lib, prm, P0, E0, dts, model, fel)
+    eP = rel_l1(interior(Pg, prm), interior(Pr, prm))
+    eE = rel_l1(interior(Eg, prm), interior(Er, prm))
+    print("edge", prm["n1"], prm["n2"], prm["n3"], eP.max(), eE)
+    assert eP.max() <= 1e-10 and eE.max() <= 1e-10, (eP, eE)
