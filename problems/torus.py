@@ -35,12 +35,15 @@ def circular_orbit_ell(r, a):
 
 
 def fm_lnh(r, th, a, ell, rin):
-    """ln h(r, theta) - ln h(r_in, pi/2) for the constant-l torus."""
+    """ln h(r, theta) - ln h(r_in, pi/2) for the constant-l torus (NaN or inf
+    where the expression has no real value, e.g. inside the horizon or on the
+    axis; callers keep only the torus body, where ln h > 0)."""
     def raw(r, th):
         sig, delta, big_a, _, _, _ = bl_quantities(r, th, a)
         s2 = np.sin(th) ** 2
-        q = np.sqrt(1.0 + 4.0 * ell * ell * sig * sig * delta / (big_a * big_a * s2))
-        return 0.5 * np.log((1.0 + q) / (sig * delta / big_a)) - 0.5 * q - 2.0 * a * r * ell / big_a
+        with np.errstate(invalid="ignore", divide="ignore"):
+            q = np.sqrt(1.0 + 4.0 * ell * ell * sig * sig * delta / (big_a * big_a * s2))
+            return 0.5 * np.log((1.0 + q) / (sig * delta / big_a)) - 0.5 * q - 2.0 * a * r * ell / big_a
     return raw(r, th) - raw(np.float64(rin), np.float64(0.5 * np.pi))
 
 

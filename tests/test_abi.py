@@ -17,7 +17,8 @@ HEADER = os.path.join(ROOT, "include", "grmhd.h")
 
 
 def header_functions():
-    text = open(HEADER).read()
+    with open(HEADER) as f:
+        text = f.read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(grmhd_[a-z_]+)\s*\(", text)))
 

@@ -43,7 +43,8 @@ def test_cache_roundtrip_and_scoping(tmp_path):
     # another library build or device does not see it
     assert tune.TileCache(path, device="devA", lib_hash="h2").get("k") is None
     assert tune.TileCache(path, device="devB", lib_hash="h1").get("k") is None
-    data = json.load(open(path))
+    with open(path) as f:
+        data = json.load(f)
     assert data["devA|h1"]["k"]["ms_per_step"] == {"sweep": 1.5, "update": 2.0}
 
 
