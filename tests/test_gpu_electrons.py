@@ -184,3 +184,20 @@ def test_electron_edge_shapes(lib, make, model, fel):
     eE = rel_l1(interior(Eg, prm), interior(Er, prm))
     print("edge", prm["n1"], prm["n2"], prm["n3"], eP.max(), eE)
     assert eP.max() <= 1e-10 and eE.max() <= 1e-10, (eP, eE)
+
+
+def test_electron_step_is_deterministic_and_tile_independent(lib):
+    """Two runs give the same bits, and so does every legal update tile (the
+    electron passes run on the update's tiles; each zone is one thread's work)."""
+    prm, P0 = problems.fm_torus(n1=72, n2=20, n3=5)
+    E0 = problems.electron_scalars(P0, prm["gam"], te_ti=0.5)
+    outs = []
+    for tile in [(64, 4), (64, 4), (32, 8), (128, 2), (16, 4)]:
+        sim = lib.Sim(prm)
+        sim.set_tiles("update", *tile)
+        P, E = sim.to_device(P0), sim.to_device(E0)
+        dt = sim.run_electrons(P, E, 3, sim.get_dt(P), "kawazura")
+        outs.append((sim.to_host(P), sim.to_host(E), dt))
+        sim.close()
+    for P, E, dt in outs[1:]:
+        assert np.array_equal(P, outs[0][0]) and np.array_equal(E, outs[0][1]) and dt == outs[0][2]
