@@ -82,16 +82,20 @@ class GpuEngine:
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(device=self.device)
         self.tiles = tiles                  # {"sweep": (tx, ty), "update": (tx, ty)} or None
-        self.jobs = {}                      # id -> [sim, state, dt]
+        self.jobs = {}                      # id -> [sim, state, dt, electrons (E, model, fel) or None]
         self.order = []                     # member ids of the current batch
         self.batch = None
         self.dirty = False
 
-    def job_bytes(self, prm):
+    def job_bytes(self, prm, electrons=False):
+        """Device bytes of a job: context, state and, with electron heating, the
+        entropies and their scratch (3 arrays of 2 doubles per padded zone)."""
         cb, sb = self.B.grmhd_context_bytes(prm)
-        return cb + sb
+        return cb + sb + (3 * sb // 4 if electrons else 0)
 
-    def start(self, job_id, prm, P0):
+    def start(self, job_id, prm, P0, electrons=None):
+        """electrons: None, or (E0, model, fel) for a job with electron heating
+        (E0 the host entropies [2, n3+6, n2+6, n1+6])."""
         if prm["recon"] != self.recon or prm["precision"] != self.precision:
             raise ValueError("every job of the engine needs its recon and precision")
         sim = None
@@ -103,11 +107,15 @@ class GpuEngine:
                     sim.set_tiles("update", *self.tiles["update"])
                 P = sim.to_device(P0)
                 dt = sim.get_dt(P)
+                el = None
+                if electrons is not None:
+                    E0, model, fel = electrons
+                    el = (sim.to_device(E0), model, fel)
         except self.B.GrmhdError as e:
             if sim is not None:
                 sim.close()
             raise JobFailed(str(e)) from e
-        self.jobs[job_id] = [sim, P, dt]
+        self.jobs[job_id] = [sim, P, dt, el]
         self.dirty = True
 
     def _harvest_dt(self):
@@ -137,7 +145,9 @@ class GpuEngine:
         if self.dirty:
             self._rebuild()
         if self.batch is not None and nsteps > 0:
-            self.batch.step([self.jobs[j][1] for j in self.order], nsteps=nsteps)
+            els = [self.jobs[j][3] for j in self.order]
+            self.batch.step([self.jobs[j][1] for j in self.order], nsteps=nsteps,
+                            electrons=els if any(e is not None for e in els) else None)
 
     def sync(self):
         self.stream.synchronize()
@@ -148,14 +158,15 @@ class GpuEngine:
         return {j: st.get(j, 0) for j in self.jobs}
 
     def finish(self, job_id, keep=False):
-        """Retire a job; returns its final host state when keep is set."""
+        """Retire a job; returns its final host state when keep is set (with
+        electron heating, the pair (P, E))."""
         if job_id in self.order:
             self._harvest_dt()
-        sim, P, _ = self.jobs.pop(job_id)
+        sim, P, _, el = self.jobs.pop(job_id)
         out = None
         if keep:
             with self.torch.cuda.stream(self.stream):
-                out = sim.to_host(P)
+                out = sim.to_host(P) if el is None else (sim.to_host(P), sim.to_host(el[0]))
         self.dirty = True
         if self.batch is not None:
             # the batch holds the job's context: drop it before the context
@@ -182,10 +193,10 @@ class FakeEngine:
         self.steps = {}
         self.cycles = []
 
-    def job_bytes(self, prm):
+    def job_bytes(self, prm, electrons=False):
         return prm["n1"] * prm["n2"] * prm["n3"] * self.bytes_per_zone
 
-    def start(self, job_id, prm, P0):
+    def start(self, job_id, prm, P0, electrons=None):
         if self.fail_at.get(job_id) == -1:
             raise JobFailed(f"job {job_id}: no finite Courant step")
         self.jobs[job_id] = prm
@@ -241,9 +252,10 @@ def percentile(values, q):
 class Server:
     """Admission in arrival order under a byte budget, continuous batching.
 
-    make_state(spec) -> (prm, P0) places a job's initial data on the host; it
-    runs while the device works on the previous cycle, for at most ``prefetch``
-    arrived jobs ahead of admission.
+    make_state(spec) -> (prm, P0), or (prm, P0, electrons) with electrons None
+    or (E0, model, fel) for electron heating, places a job's initial data on
+    the host; it runs while the device works on the previous cycle, for at
+    most ``prefetch`` arrived jobs ahead of admission.
     """
 
     def __init__(self, engine, make_state, budget_bytes, clock=None, quantum=25, prefetch=8,
@@ -267,8 +279,9 @@ class Server:
             if n >= self.prefetch:
                 break
             if r.prm is None:
-                r.prm, r.state = self.make_state(r.spec)
-                r.bytes = self.engine.job_bytes(r.prm)
+                made = self.make_state(r.spec)
+                r.prm, r.state = made[0], tuple(made[1:])
+                r.bytes = self.engine.job_bytes(r.prm, electrons=len(r.state) > 1 and r.state[1] is not None)
             n += 1
 
     def run(self, specs):
@@ -295,7 +308,7 @@ class Server:
                     break
                 queue.popleft()
                 try:
-                    self.engine.start(r.spec.id, r.prm, r.state)
+                    self.engine.start(r.spec.id, r.prm, *r.state)
                 except JobFailed as e:
                     # retired at once; the other jobs never see it
                     r.state = None
@@ -401,12 +414,16 @@ def identity_check(report, specs, make_state, recon, precision, sample, device="
             continue
         spec = by_id[jid]
         eng = GpuEngine(recon, precision, device=device, tiles=tiles)
-        prm, P0 = make_state(spec)
-        eng.start(jid, prm, P0)
+        made = make_state(spec)
+        eng.start(jid, *made)
         eng.advance(spec.steps)
         eng.sync()
         alone = eng.finish(jid, keep=True)
-        out[jid] = bool(np.array_equal(alone, results[jid]))
+        mixed = results[jid]
+        if isinstance(alone, tuple):
+            out[jid] = isinstance(mixed, tuple) and all(np.array_equal(a, b) for a, b in zip(alone, mixed))
+        else:
+            out[jid] = bool(np.array_equal(alone, mixed))
     return out
 
 
@@ -423,6 +440,8 @@ def main(argv=None):
     ap.add_argument("--max-steps", type=int, default=2000)
     ap.add_argument("--identity", type=int, default=8, help="jobs re-run alone for the identity check")
     ap.add_argument("--tune", action="store_true", help="autotune tiles on the first job's grid")
+    ap.add_argument("--electrons", choices=["constant", "kawazura", "werner", "rowan", "howes", "sharma"],
+                    default=None, help="evolve the torus jobs with electron heating by this model")
     args = ap.parse_args(argv)
 
     import sys
@@ -436,12 +455,15 @@ def main(argv=None):
     specs = poisson_stream(args.jobs, args.lam, args.seed, steps=(args.min_steps, args.max_steps))
 
     def make_state(spec):
-        return spec.make(recon=recon, precision=precision)
+        prm, P0 = spec.make(recon=recon, precision=precision)
+        if args.electrons and spec.kind == "torus":
+            return prm, P0, (problems.electron_scalars(P0, prm["gam"]), args.electrons, 0.5)
+        return prm, P0
 
     tiles = None
     if args.tune:
         from . import tune
-        prm, P0 = make_state(max(specs, key=lambda s: s.zones))
+        prm, P0 = make_state(max(specs, key=lambda s: s.zones))[:2]
         tiles = tune.tune_problem(prm, P0)
     rng = np.random.default_rng(args.seed + 1000)
     sample = sorted(int(x) for x in rng.choice(len(specs), size=min(args.identity, len(specs)), replace=False))
@@ -465,7 +487,8 @@ def main(argv=None):
     summ["config"] = {"workload": f"poisson stream of {args.jobs} torus/Bondi jobs",
                       "lam_per_s": args.lam, "seed": args.seed, "budget_gb": args.budget_gb,
                       "recon": args.recon, "precision": args.precision, "quantum": args.quantum,
-                      "steps": [args.min_steps, args.max_steps], "tiles": tiles}
+                      "steps": [args.min_steps, args.max_steps], "tiles": tiles,
+                      "electrons": args.electrons}
     print(json.dumps(summ), flush=True)
     return 0 if all(ident.values()) and not rep.failed else 1
 

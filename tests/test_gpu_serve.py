@@ -74,6 +74,35 @@ def test_a_job_that_cannot_start_is_failed_and_the_others_are_untouched(lib):
     assert ident == {0: True, 2: True}
 
 
+def test_stream_with_electron_heating_matches_jobs_run_alone(lib):
+    """Jobs with electron heating (two models) and without share the served
+    batch; every job's final primitives and entropies equal, bit for bit, the
+    ones it reaches alone."""
+    specs = [
+        JobSpec(0, "torus", 48, 32, 8, a=0.9, steps=7, arrival=0.0),
+        JobSpec(1, "bondi", 40, 24, 4, a=0.3, steps=5, arrival=0.0),
+        JobSpec(2, "torus", 64, 20, 6, a=0.5, steps=9, arrival=0.05),
+        JobSpec(3, "box", 16, 16, 16, steps=6, arrival=0.1),
+    ]
+    heat = {0: ("howes", 0.0), 3: ("constant", 0.4)}
+    clean = make_state(problems.RECON_MC, problems.FP64)
+
+    def mk(spec):
+        prm, P0 = clean(spec)
+        if spec.id in heat:
+            return prm, P0, (problems.electron_scalars(P0, prm["gam"], te_ti=0.5),) + heat[spec.id]
+        return prm, P0
+
+    eng = GpuEngine(problems.RECON_MC, problems.FP64)
+    srv = Server(eng, mk, 1 << 40, quantum=3, keep=[s.id for s in specs])
+    rep = srv.run(specs)
+    assert rep.summary()["completed"] == 4 and not rep.failed
+    res = rep.results()
+    assert isinstance(res[0], tuple) and isinstance(res[3], tuple) and not isinstance(res[1], tuple)
+    ident = identity_check(rep, specs, mk, problems.RECON_MC, problems.FP64, [s.id for s in specs])
+    assert ident == {s.id: True for s in specs}
+
+
 def test_tuned_tiles_do_not_change_a_served_job(lib):
     spec = JobSpec(0, "torus", 48, 32, 8, a=0.9, steps=4)
     mk = make_state(problems.RECON_MC, problems.FP64)
