@@ -42,3 +42,19 @@ def test_bad_input_is_refused(tmp_path):
     np.savez(path, format=np.int64(1), problem=np.array([{"n1": 8}], dtype=object), P=P, dt=1.0, t=0.0, step=0)
     with pytest.raises(ValueError):
         checkpoint.load(path)
+
+
+def test_round_trip_with_electron_entropies(tmp_path):
+    prm, P = problems.fm_torus(n1=24, n2=12, n3=4)
+    E = problems.electron_scalars(P, prm["gam"], te_ti=0.5)
+    path = str(tmp_path / "e.npz")
+    checkpoint.save(path, prm, P, 0.01, E=E, heat=("kawazura", 0.0))
+    ck = checkpoint.load(path)
+    assert np.array_equal(ck.E, E) and ck.heat == ("kawazura", 0.0)
+    plain = str(tmp_path / "p.npz")
+    checkpoint.save(plain, prm, P, 0.01)
+    assert checkpoint.load(plain).E is None and checkpoint.load(plain).heat is None
+    with pytest.raises(ValueError):
+        checkpoint.save(str(tmp_path / "x.npz"), prm, P, 0.01, E=E[:, :-1], heat=("howes", 0.0))
+    with pytest.raises(ValueError):
+        checkpoint.save(str(tmp_path / "y.npz"), prm, P, 0.01, E=E)

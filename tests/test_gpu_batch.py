@@ -221,13 +221,16 @@ def test_a_non_finite_state_is_an_error_of_the_step(lib):
     sim.close()
 
 
-def test_batch_with_electrons_equals_each_job_alone(lib):
+@pytest.mark.parametrize("recon,precision", [(problems.RECON_MC, problems.FP64),
+                                             (problems.RECON_WENO5, problems.MIXED)], ids=["mc_fp64", "weno5_mixed"])
+def test_batch_with_electrons_equals_each_job_alone(lib, recon, precision):
     """Electron heating in the batch: jobs with and without entropies, with
     different heating models, share every grid; each job's primitives,
     entropies and step size equal, bit for bit, a host loop of
     grmhd_step_electrons (or grmhd_step) on its own context."""
-    jobs = [problems.fm_torus(n1=48, n2=28, n3=4), problems.bondi(n1=40, n2=24, n3=2, a=0.7),
-            problems.linear_modes(n=12, n3=9, kvec=(1, 1, 0))]
+    kw = dict(recon=recon, precision=precision)
+    jobs = [problems.fm_torus(n1=48, n2=28, n3=4, **kw), problems.bondi(n1=40, n2=24, n3=2, a=0.7, **kw),
+            problems.linear_modes(n=12, n3=9, kvec=(1, 1, 0), **kw)]
     heat = [("howes", 0.0), None, ("constant", 0.3)]
     nsteps = 4
     alone = []

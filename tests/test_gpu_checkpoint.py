@@ -96,3 +96,32 @@ def test_batch_restart(lib, tmp_path):
     for s, P, ref in zip(sims, states, refs):
         assert np.array_equal(s.to_host(P), ref)
     b.close()
+
+
+def test_restart_with_electron_heating(lib, tmp_path):
+    """A run with electron heating stopped, written (primitives, entropies,
+    model) and continued in a fresh context equals the run that never stopped."""
+    prm, P0 = problems.fm_torus(n1=48, n2=28, n3=4)
+    E0 = problems.electron_scalars(P0, prm["gam"], te_ti=0.5)
+    heat = ("howes", 0.0)
+    a = lib.Sim(prm)
+    Pa, Ea = a.to_device(P0), a.to_device(E0)
+    dt0 = a.get_dt(Pa)
+    dt_a = a.run_electrons(Pa, Ea, 6, dt0, *heat)
+    ref_P, ref_E = a.to_host(Pa), a.to_host(Ea)
+    a.close()
+
+    b = lib.Sim(prm)
+    Pb, Eb = b.to_device(P0), b.to_device(E0)
+    dt_b = b.run_electrons(Pb, Eb, 3, dt0, *heat)
+    path = str(tmp_path / "mid_e.npz")
+    checkpoint.save(path, prm, b.to_host(Pb), dt_b, step=3, E=b.to_host(Eb), heat=heat)
+    b.close()
+
+    ck = checkpoint.load(path)
+    c = lib.Sim(ck.prm)
+    Pc, Ec = c.to_device(ck.P), c.to_device(ck.E)
+    dt_c = c.run_electrons(Pc, Ec, 3, ck.dt, *ck.heat)
+    assert dt_c == dt_a
+    assert np.array_equal(c.to_host(Pc), ref_P) and np.array_equal(c.to_host(Ec), ref_E)
+    c.close()

@@ -201,3 +201,23 @@ def test_electron_step_is_deterministic_and_tile_independent(lib):
         sim.close()
     for P, E, dt in outs[1:]:
         assert np.array_equal(P, outs[0][0]) and np.array_equal(E, outs[0][1]) and dt == outs[0][2]
+
+
+def test_full_size_mixed_precision_slab(lib):
+    """Mixed precision (FP32 faces, WENO5) with electron heating on the full
+    288 x 128 x 128 torus: one step against the FP64 oracle on an x3 slab,
+    within the mixed-precision bar."""
+    prm, P0 = problems.fm_torus(recon=problems.RECON_WENO5, precision=problems.MIXED)
+    E0 = problems.electron_scalars(P0, prm["gam"], te_ti=0.5)
+    dt = 0.005
+    sim = lib.Sim(prm)
+    P, E = sim.to_device(P0), sim.to_device(E0)
+    sim.step_electrons(P, E, dt, el.MODEL_KAWAZURA, 0.0, want_dt_next=False)
+    Pg, Eg = interior(sim.to_host(P), prm), interior(sim.to_host(E), prm)
+    sim.close()
+    g = oracle.Grid(dict(prm, precision=problems.FP64))
+    Pr, Er = el.step_window(P0, E0, g, dt, 40, 41, el.MODEL_KAWAZURA, 0.0)
+    eP = rel_l1(Pg[:, 40:41], Pr)
+    eE = rel_l1(Eg[:, 40:41], Er)
+    print("mixed slab 40", eP.max(), eE)
+    assert eP.max() <= 1e-5 and eE.max() <= 1e-5, (eP, eE)
