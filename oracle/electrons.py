@@ -36,10 +36,12 @@ E6  f_e: a constant, or one of four models as functions of beta_i = P_i /
                      beta_max = 1/(4 sigma_w), (1 - beta_i/beta_max) floored at 0;
       Howes 2010:    with theta = T_i/T_e,
                      Q_i/Q_e = 0.92 (c2^2 + beta_i^x)/(c3^2 + beta_i^x) sqrt(m_p theta / m_e) exp(-1/beta_i),
-                     x = 2 - 0.2 log10 theta, c2 = 1.6/theta,
-                     c3 = 18 + 5 log10 theta (theta > 1) or 18 (beta_i^x capped at e^700);
-      Sharma 2007:   Q_i/Q_e = sqrt(T_i/T_e) / 3 (the turbulent-heating ratio
-                     as commonly quoted from that work; no formula in the paper);
+                     x = 2 - 0.2 log10 theta; for theta > 1 c2 = 1.6/theta and
+                     c3 = 18 + 5 log10 theta, for theta <= 1 c2 = 1.2/theta and
+                     c3 = 18 (the two branches of that fit; beta_i^x capped at e^700);
+      Sharma 2007:   Q_e/Q_i = sqrt(T_e/T_i) / 3, i.e. Q_i/Q_e = 3 sqrt(T_i/T_e)
+                     (the electron-to-ion ratio that work fits; no formula in
+                     the paper);
     with f_e = 1/(1 + Q_i/Q_e) where a ratio is given.
 
 Parity status: E1-E5 are pinned by properties of the equations (a passive
@@ -49,8 +51,9 @@ rho^(gamma - gamma_e) factor; electrons holding and receiving the same fraction
 of entropy and heat keep it; the bounds hold). The model formulas of E6 are the
 cited papers' as read here: parity unpinned beyond their published limits
 (f_e -> 1 as beta_i -> 0 for Kawazura and Howes, Q_i/Q_e -> 35 at high beta_i
-for Kawazura, Werner between 1/4 and 1/2, Rowan at most 1/2, Sharma 3/4 at
-T_e = T_i).
+for Kawazura, Werner between 1/4 and 1/2, Rowan at most 1/2, Sharma 1/4 at
+T_e = T_i). The Howes and Sharma coefficients in particular are read from the
+cited works without a check against their tabulated values: parity unpinned.
 """
 
 import numpy as np
@@ -152,14 +155,14 @@ def heating_fraction(model, fel, rho, u, kel, bsq, gam):
     if model == MODEL_HOWES:
         theta = pi / np.maximum(pe, 1e-300)
         lt = np.log10(theta)
-        c2 = 1.6 / theta
+        c2 = np.where(theta > 1.0, 1.6, 1.2) / theta
         c3 = np.where(theta > 1.0, 18.0 + 5.0 * lt, 18.0)
         x = 2.0 - 0.2 * lt
         bx = np.exp(np.minimum(x * np.log(beta), 700.0))   # beta^x, kept finite
         qi_qe = 0.92 * (c2 * c2 + bx) / (c3 * c3 + bx) * np.sqrt(MP_ME * theta) * np.exp(-1.0 / beta)
         return 1.0 / (1.0 + qi_qe)
     if model == MODEL_SHARMA:
-        qi_qe = np.sqrt(pi / np.maximum(pe, 1e-300)) / 3.0
+        qi_qe = 3.0 * np.sqrt(pi / np.maximum(pe, 1e-300))
         return 1.0 / (1.0 + qi_qe)
     raise ValueError(f"unknown heating model {model}")
 
@@ -237,7 +240,7 @@ def step_window(P, E, grid, dt, k0, k1, model=MODEL_CONSTANT, fel=0.5):
     ks = np.arange(k0 - M1 - NG, k1 + M1 + NG) % n3 + NG
     blk, eblk = full[:, ks], fullE[:, ks]
     it1 = (slice(None), slice(NG, blk.shape[1] - NG), slice(NG, NG + n2), slice(NG, NG + n1))
-    Ph_i, _, _, m1 = substep(blk, blk[it1], grid, 0.5 * dt, mass_flux=True)
+    Ph_i, _, _, m1 = substep(blk, blk[it1], grid, 0.5 * dt, mass_flux=True, window=True)
     Eh_i = electron_substep(eblk, eblk[it1], blk[it1], Ph_i, m1, grid, 0.5 * dt, model, fel)
     ph, eh = blk.copy(), eblk.copy()
     ph[it1], eh[it1] = Ph_i, Eh_i
@@ -247,6 +250,6 @@ def step_window(P, E, grid, dt, k0, k1, model=MODEL_CONSTANT, fel=0.5):
     w = (k1 - k0) + 2 + 2 * NG
     blk2, eblk2 = ph[:, off:off + w], eh[:, off:off + w]
     inner = (slice(None), slice(off + NG, off + NG + (k1 - k0) + 2), slice(NG, NG + n2), slice(NG, NG + n1))
-    Pn_i, _, _, m2 = substep(blk2, blk[inner], grid, dt, mass_flux=True)
+    Pn_i, _, _, m2 = substep(blk2, blk[inner], grid, dt, mass_flux=True, window=True)
     En_i = electron_substep(eblk2, eblk[inner], blk[inner], Pn_i, m2, grid, dt, model, fel)
     return Pn_i[:, 1:-1], En_i[:, 1:-1]

@@ -272,49 +272,78 @@ def floors(P, geo, r, prm, mask=None):
     return P
 
 
-def fixup(P, failed):
+def _neighbour(a, off, wrap, fill):
+    """b[x] = a[x + off] over the last three axes (k, j, i); an axis with
+    wrap[axis] True is periodic, otherwise out-of-range entries are ``fill``."""
+    b = a
+    for ax, (o, w) in enumerate(zip(off, wrap)):
+        if o == 0:
+            continue
+        axis = b.ndim - 3 + ax
+        if w:
+            b = np.roll(b, -o, axis=axis)
+        else:
+            n = b.shape[axis]
+            out = np.full_like(b, fill)
+            src = [slice(None)] * b.ndim
+            dst = [slice(None)] * b.ndim
+            src[axis] = slice(max(0, o), n + min(0, o))
+            dst[axis] = slice(max(0, -o), n - max(0, o))
+            out[tuple(dst)] = b[tuple(src)]
+            b = out
+    return b
+
+
+def fixup(P, failed, wrap=(False, False, False)):
     """Repair zones whose inversion failed, in place.
 
     Reading (the paper only says the bounds avoid catastrophic failures): a
     failed zone takes the mean of the hydrodynamic primitives (rho, u, u~) of
     its non-failed neighbours among the 26 around it, read from the array
-    before any repair and restricted to the block's interior; with none it
-    keeps what it holds. B is never touched (it comes straight from U).
+    before any repair; with none it keeps what it holds. B is never touched
+    (it comes straight from U). Neighbours are taken across periodic
+    directions (``wrap``, in (x3, x2, x1) = array axis order), so the repair
+    of a zone does not depend on where the periodic seam of the domain lies
+    (or, for a domain split into parts, on where the part boundaries lie);
+    across a non-periodic edge there are no neighbours.
     """
     if not failed.any():
         return P
     ok = ~failed
     acc = np.zeros((5,) + failed.shape)
     cnt = np.zeros(failed.shape)
-    n3, n2, n1 = failed.shape
     for dk in (-1, 0, 1):
         for dj in (-1, 0, 1):
             for di in (-1, 0, 1):
                 if dk == dj == di == 0:
                     continue
-                dst = (slice(max(0, -dk), n3 - max(0, dk)), slice(max(0, -dj), n2 - max(0, dj)),
-                       slice(max(0, -di), n1 - max(0, di)))
-                src = (slice(max(0, dk), n3 + min(0, dk)), slice(max(0, dj), n2 + min(0, dj)),
-                       slice(max(0, di), n1 + min(0, di)))
-                w = ok[src]
-                acc[(slice(None),) + dst] += np.where(w, P[(slice(0, 5),) + src], 0.0)
-                cnt[dst] += w
+                w = _neighbour(ok, (dk, dj, di), wrap, False)
+                acc += np.where(w, _neighbour(P[:5], (dk, dj, di), wrap, 0.0), 0.0)
+                cnt += w
     fix = failed & (cnt > 0)
     with np.errstate(all="ignore"):
         P[:5] = np.where(fix, acc / cnt, P[:5])
     return P
 
 
+def periodic_axes(prm, window=False):
+    """(x3, x2, x1) periodicity of a block for the fixup; a window of x3 planes
+    cut from a larger domain is not periodic in x3."""
+    per = [prm["bc"][d][0] == BC_PERIODIC for d in range(3)]
+    return (per[2] and not window, per[1], per[0])
+
+
 # ----------------------------------------------------------------------------- substep / step
 
-def substep(Ps, Pb, grid, dt, mass_flux=False):
+def substep(Ps, Pb, grid, dt, mass_flux=False, window=False):
     """One substep on a padded block.
 
     Ps: flux-state primitives with ghosts filled (padded block); Pb: base-state
     primitives on the block interior. Returns (P_new interior, failed mask,
     ctop maxima per direction over the interior faces), and with
     ``mass_flux`` also the three mass-flux arrays (component 0 of the face
-    fluxes after Flux-CT, padded grid).
+    fluxes after Flux-CT, padded grid). ``window``: the block is a window of x3
+    planes of a larger domain (its fixup does not wrap in x3).
     """
     prm = grid.prm
     gam = prm["gam"]
@@ -341,7 +370,7 @@ def substep(Ps, Pb, grid, dt, mass_flux=False):
     if prm["floors"]:
         floors(Pn, geo, grid.r[J, I], prm)
     if failed.any():
-        fixup(Pn, failed)
+        fixup(Pn, failed, periodic_axes(prm, window))
         if prm["floors"]:
             floors(Pn, geo, grid.r[J, I], prm, mask=failed)
     cmax = (np.nanmax(C1[K, J, NG:NG + n1 + 1]), np.nanmax(C2[K, NG:NG + n2 + 1, I]),
@@ -411,7 +440,7 @@ def step_window(P, grid, dt, k0, k1):
     ks = np.arange(k0 - M1 - NG, k1 + M1 + NG) % n3 + NG
     blk = full[:, ks]
     it1 = (slice(None), slice(NG, blk.shape[1] - NG), slice(NG, NG + n2), slice(NG, NG + n1))
-    Ph_i, _, _ = substep(blk, blk[it1], grid, 0.5 * dt)
+    Ph_i, _, _ = substep(blk, blk[it1], grid, 0.5 * dt, window=True)
     ph = blk.copy()
     ph[it1] = Ph_i
     fill_ghosts(ph, grid, do_x3=False)
@@ -419,7 +448,7 @@ def step_window(P, grid, dt, k0, k1):
     off = (M1 + NG) - (1 + NG)
     blk2 = ph[:, off:off + (k1 - k0) + 2 + 2 * NG]
     base = blk[:, off + NG:off + NG + (k1 - k0) + 2, NG:NG + n2, NG:NG + n1]
-    Pn_i, _, _ = substep(blk2, base, grid, dt)
+    Pn_i, _, _ = substep(blk2, base, grid, dt, window=True)
     return Pn_i[:, 1:-1]
 
 
@@ -442,7 +471,7 @@ def cons_to_prim(U, guess, grid, do_floors=True, do_fixup=True):
     if do_floors and grid.prm["floors"]:
         floors(P, geo, grid.r[J, I], grid.prm)
     if do_fixup and failed.any():
-        fixup(P, failed)
+        fixup(P, failed, periodic_axes(grid.prm))
         if do_floors and grid.prm["floors"]:
             floors(P, geo, grid.r[J, I], grid.prm, mask=failed)
     return P, failed

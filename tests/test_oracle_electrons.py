@@ -206,9 +206,19 @@ def test_heating_model_limits():
     # T_i = T_e, Q_i/Q_e -> 0.92 sqrt(m_p / m_e)
     assert _fe(el.MODEL_HOWES, beta=1e-3) == pytest.approx(1.0, abs=1e-12)
     assert _fe(el.MODEL_HOWES, beta=1e6) == pytest.approx(1.0 / (1.0 + 0.92 * np.sqrt(el.MP_ME)), rel=1e-6)
-    # Sharma et al. 2007: Q_i/Q_e = sqrt(T_i/T_e)/3, so 3/4 at T_e = T_i
-    assert _fe(el.MODEL_SHARMA, beta=1.0) == pytest.approx(0.75, rel=1e-12)
-    assert _fe(el.MODEL_SHARMA, beta=1.0, te_ti=0.25) == pytest.approx(0.6, rel=1e-12)
+    # Sharma et al. 2007: Q_e/Q_i = sqrt(T_e/T_i)/3, so 1/4 at T_e = T_i and
+    # 1/7 at T_i = 4 T_e; the electron share grows with T_e/T_i
+    assert _fe(el.MODEL_SHARMA, beta=1.0) == pytest.approx(0.25, rel=1e-12)
+    assert _fe(el.MODEL_SHARMA, beta=1.0, te_ti=0.25) == pytest.approx(1.0 / 7.0, rel=1e-12)
+    assert _fe(el.MODEL_SHARMA, beta=1.0, te_ti=4.0) == pytest.approx(0.4, rel=1e-12)
+    # Howes 2010 at beta_i = 1 (beta_i^x = 1 for any x): which branch of the
+    # fit applies on each side of T_i = T_e (c2 = 1.2/theta, c3 = 18 for
+    # T_i <= T_e; 1.6/theta and 18 + 5 log10 theta above). This checks the
+    # branch selection of the reading only: the coefficients are parity unpinned.
+    for r, c2, c3 in ((2.0, 1.2 * 2.0, 18.0), (0.5, 1.6 * 0.5, 18.0 + 5.0 * np.log10(2.0))):
+        theta = 1.0 / r
+        q = 0.92 * (c2 ** 2 + 1.0) / (c3 ** 2 + 1.0) * np.sqrt(el.MP_ME * theta) * np.exp(-1.0)
+        assert _fe(el.MODEL_HOWES, beta=1.0, te_ti=r) == pytest.approx(1.0 / (1.0 + q), rel=1e-9)
     # all models are fractions
     for m in (el.MODEL_KAWAZURA, el.MODEL_WERNER, el.MODEL_ROWAN, el.MODEL_HOWES, el.MODEL_SHARMA):
         for b in (1e-8, 1e-2, 1.0, 1e2, 1e8):

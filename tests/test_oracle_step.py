@@ -290,3 +290,65 @@ def test_window_step_equals_full_step():
     assert np.array_equal(win, ref)
     win0 = oracle.step_window(P, g, dt, 0, 1)     # wraps around the periodic x3 edge
     assert np.array_equal(win0, interior(full, prm)[:, 0:1])
+
+
+def test_fixup_wraps_periodic_directions():
+    """Across a periodic direction the neighbours of a failed zone are the
+    zones on the other side of the seam: a brute-force loop with modular
+    indices, and invariance under shifts of the seam (np.roll)."""
+    rng = np.random.default_rng(17)
+    P = rng.normal(size=(8, 5, 6, 7))
+    failed = rng.random((5, 6, 7)) < 0.25
+    failed[0, 0, 0] = failed[4, 5, 6] = True           # corners touch three seams
+    for wrap in ((True, True, True), (True, False, True), (False, True, False)):
+        ref = P.copy()
+        for (k, j, i) in zip(*np.nonzero(failed)):
+            acc, c = np.zeros(5), 0
+            for dk in (-1, 0, 1):
+                for dj in (-1, 0, 1):
+                    for di in (-1, 0, 1):
+                        if (dk, dj, di) == (0, 0, 0):
+                            continue
+                        idx = []
+                        for x, dx, n, w in ((k, dk, 5, wrap[0]), (j, dj, 6, wrap[1]), (i, di, 7, wrap[2])):
+                            y = x + dx
+                            if w:
+                                y %= n
+                            elif not 0 <= y < n:
+                                y = None
+                            idx.append(y)
+                        if None in idx or failed[tuple(idx)]:
+                            continue
+                        acc += P[(slice(0, 5),) + tuple(idx)]
+                        c += 1
+            if c:
+                ref[:5, k, j, i] = acc / c
+        got = fixup(P.copy(), failed, wrap)
+        assert np.allclose(got, ref, rtol=1e-14, atol=1e-15), wrap
+    # seam placement does not matter where everything is periodic
+    full = (True, True, True)
+    base = fixup(P.copy(), failed, full)
+    for shift in ((2, 0, 0), (0, 3, 0), (0, 0, 5), (1, 2, 3)):
+        rolled = fixup(np.roll(P, shift, axis=(1, 2, 3)), np.roll(failed, shift, axis=(0, 1, 2)), full)
+        assert np.array_equal(np.roll(rolled, [-s for s in shift], axis=(1, 2, 3)), base), shift
+
+
+def test_step_with_a_failed_zone_at_the_seam_is_translation_invariant():
+    """On a periodic box a zone whose inversion fails next to the x3 seam is
+    repaired from the zones across the seam: rolling the initial state along
+    x3 rolls the result. A cold zone moving at Lorentz factor ~ 40 into gas at
+    rest makes the inversions around it fail in the corrector."""
+    prm, P0 = problems.linear_modes(n=8)
+    g = oracle.Grid(prm)
+    Q = P0.copy()
+    Q[1, NG, NG + 3, NG + 3] = 1e-6
+    Q[2, NG, NG + 3, NG + 3] = 40.0
+    dt = oracle.get_dt(Q, g)
+    a, _, info = oracle.step(Q, g, dt)
+    assert info["fail_predictor"] + info["fail_corrector"] > 0
+    for s in (1, 3):
+        R = Q.copy()
+        R[:, NG:NG + 8] = np.roll(Q[:, NG:NG + 8], s, axis=1)
+        b, _, _ = oracle.step(R, g, dt)
+        bi = np.roll(interior(b, prm), -s, axis=1)
+        assert np.allclose(bi, interior(a, prm), rtol=1e-12, atol=1e-14), s
