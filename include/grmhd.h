@@ -138,8 +138,10 @@ GRMHD_API int grmhd_get_dt(grmhd_ctx *ctx, double *P, double *dt);
 
 /* One second-order predictor-corrector step of size dt, in place on P
  * (ghosts refilled). dt_next (nullable, host): the Courant step from the
- * corrector's signal speeds; synchronises when given. Returns GRMHD_ESTATE if
- * a non-finite signal speed appeared (only checked when dt_next is given). */
+ * corrector's signal speeds. Synchronises (it reads the step's counters back).
+ * Returns GRMHD_ESTATE, whether or not dt_next is given, if the step stored a
+ * non-finite value anywhere in P (a failed inversion that the fixup repairs
+ * does not count) or a corrector signal speed is not finite. */
 GRMHD_API int grmhd_step(grmhd_ctx *ctx, double *P, double dt, double *dt_next);
 
 /* nsteps predictor-corrector steps in place on P with the step size kept on
@@ -148,8 +150,9 @@ GRMHD_API int grmhd_step(grmhd_ctx *ctx, double *P, double dt, double *dt_next);
  * host loop of dt <- min(dt_next, 1.3 dt) around grmhd_step, so the results
  * are identical; the host does not wait between steps. dt (host, in/out): the
  * first step's size on entry, the size for the step after the last on exit.
- * Synchronises once at the end. Returns GRMHD_ESTATE if a non-finite signal
- * speed appeared (dt then stops growing). */
+ * Synchronises once at the end. Returns GRMHD_ESTATE if a step stored a
+ * non-finite value in P or met a non-finite signal speed (dt then stops
+ * growing). */
 GRMHD_API int grmhd_run(grmhd_ctx *ctx, double *P, int32_t nsteps, double *dt);
 
 /* The pieces of a step, for drivers that own the ghost zones of some
@@ -172,6 +175,37 @@ GRMHD_API int grmhd_fill_ghosts(grmhd_ctx *ctx, double *P, const double *base);
 GRMHD_API int grmhd_substep(grmhd_ctx *ctx, const double *Ps, const double *Pb, double *Pout, double dt,
                             int32_t want_speeds);
 GRMHD_API int grmhd_speeds(grmhd_ctx *ctx, double ctop[3]);
+/* grmhd_substep in two halves, for a split domain whose parts must exchange
+ * the new state and the failure flags of their boundary planes before the
+ * fixup (so that a failed zone next to a part boundary is repaired from the
+ * same neighbours as in the undivided domain).
+ *
+ * grmhd_update: the substep without the fixup; P_out holds the bounded
+ * inversion (a failed zone keeps the flux state's hydro primitives) and flags
+ * (caller-owned int8 device array with the layout of one state variable,
+ * [n3+6][n2+6][n1p]) is set to 1 on failed interior zones and 0 on the others
+ * (its ghost cells are not written). Asynchronous.
+ * grmhd_fixup: repairs every flagged interior zone of P, after grmhd_update on
+ * the same context, from the mean of the hydro primitives of its non-flagged
+ * neighbours among the 26 (the values grmhd_update stored, whatever the order),
+ * then applies the bounds to it. Across a periodic direction the neighbours
+ * are the zones on the other side of the seam; across a side whose bit is set
+ * in halo_sides (bit 2 d + s for direction d = 0, 1, 2 and side s = 0 lower,
+ * 1 upper) they are the first ghost layer of P and flags, which the caller has
+ * filled with the neighbouring part's values and flags; across any other edge
+ * there are none. grmhd_substep(..., Pout, ...) is grmhd_update followed by
+ * grmhd_fixup with the context's own flags and no halo sides. Asynchronous.
+ * Errors: EINVAL (NULL, dt, a halo side on a periodic direction). */
+GRMHD_API int grmhd_update(grmhd_ctx *ctx, const double *Ps, const double *Pb, double *Pout, double dt,
+                           int32_t want_speeds, int8_t *flags);
+GRMHD_API int grmhd_fixup(grmhd_ctx *ctx, double *P, const int8_t *flags, int32_t halo_sides);
+/* The Courant step of a domain split into nparts contexts: ctop (host,
+ * nparts x 3) holds each part's grmhd_speeds; with c_d the maximum over the
+ * parts, dt = cfl / sum_d (c_d / dx_d) (the rule grmhd_step uses for dt_next),
+ * cfl and dx_d from ctx (any part: they share both). No device work.
+ * Errors: EINVAL (NULL, nparts < 1, a negative speed), ESTATE (a non-finite
+ * speed). */
+GRMHD_API int grmhd_courant_dt(const grmhd_ctx *ctx, const double *ctop, int32_t nparts, double *dt);
 
 /* ---- Electron heating (Implementation Notes: iharm3D tracks the dissipation
  * and splits it between ions and electrons after Ressler et al. 2015, with the
@@ -198,8 +232,8 @@ GRMHD_API int grmhd_speeds(grmhd_ctx *ctx, double ctop[3]);
  * models (fel ignored). The ghost zones of E follow the primitives' rules
  * without the axis sign change and the inflow fix. The first call on a context
  * allocates 4 doubles per padded zone of scratch, held until grmhd_free.
- * dt_next and the errors as grmhd_step; EINVAL also for an unknown model or
- * fel outside [0, 1]. */
+ * dt_next and the errors as grmhd_step (a non-finite entropy also gives
+ * GRMHD_ESTATE); EINVAL also for an unknown model or fel outside [0, 1]. */
 enum {
   GRMHD_HEAT_CONSTANT = 0, GRMHD_HEAT_KAWAZURA = 1, GRMHD_HEAT_WERNER = 2, GRMHD_HEAT_ROWAN = 3,
   GRMHD_HEAT_HOWES = 4, GRMHD_HEAT_SHARMA = 5

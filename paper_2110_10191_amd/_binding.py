@@ -14,7 +14,7 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 # every symbol include/grmhd.h declares
 EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
-    "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_speeds", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
+    "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_update", "grmhd_fixup", "grmhd_speeds", "grmhd_courant_dt", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step", "grmhd_batch_step_electrons",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
@@ -87,6 +87,9 @@ def _load():
         "grmhd_fill_ghosts": ([vp, vp, vp], ctypes.c_int),
         "grmhd_substep": ([vp, vp, vp, vp, ctypes.c_double, i32], ctypes.c_int),
         "grmhd_speeds": ([vp, dp], ctypes.c_int),
+        "grmhd_update": ([vp, vp, vp, vp, ctypes.c_double, i32, vp], ctypes.c_int),
+        "grmhd_fixup": ([vp, vp, vp, i32], ctypes.c_int),
+        "grmhd_courant_dt": ([vp, dp, i32, dp], ctypes.c_int),
         "grmhd_divb": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step_failures": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -227,10 +230,27 @@ def grmhd_substep(ctx, Ps, Pb, Pout, dt, want_speeds=False):
     _check(lib.grmhd_substep(ctx, _ptr(Ps), _ptr(Pb), _ptr(Pout), float(dt), 1 if want_speeds else 0), ctx)
 
 
+def grmhd_update(ctx, Ps, Pb, Pout, dt, flags, want_speeds=False):
+    _check(lib.grmhd_update(ctx, _ptr(Ps), _ptr(Pb), _ptr(Pout), float(dt), 1 if want_speeds else 0, _ptr(flags)), ctx)
+
+
+def grmhd_fixup(ctx, P, flags, halo_sides=0):
+    _check(lib.grmhd_fixup(ctx, _ptr(P), _ptr(flags), int(halo_sides)), ctx)
+
+
 def grmhd_speeds(ctx):
     v = (ctypes.c_double * 3)()
     _check(lib.grmhd_speeds(ctx, v), ctx)
     return tuple(v)
+
+
+def grmhd_courant_dt(ctx, speeds):
+    """Courant step of a split domain from each part's (ctop_1, ctop_2, ctop_3)."""
+    flat = [float(c) for part in speeds for c in part]
+    arr = (ctypes.c_double * len(flat))(*flat)
+    dt = ctypes.c_double()
+    _check(lib.grmhd_courant_dt(ctx, arr, len(speeds), ctypes.byref(dt)), ctx)
+    return dt.value
 
 
 def grmhd_divb(ctx, P):

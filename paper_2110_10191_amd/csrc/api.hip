@@ -130,9 +130,12 @@ struct ElectronPass {
 // Dirichlet ghosts). dt_dev: when not null the step is dt_scale * *dt_dev (read
 // on the device). fill = false leaves the ghost zones of Ps as they are.
 // el: also advect and heat the electron entropies.
+// flags: the failure flags the update writes (the context's own when null);
+// fix: run the fixup (with the context's flags and no halo sides) as well.
 int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop,
             const double* dt_dev = nullptr, double dt_scale = 1.0, bool fill = true,
-            const ElectronPass* el = nullptr) {
+            const ElectronPass* el = nullptr, int8_t* flags = nullptr, bool fix = true) {
+  int8_t* fl = flags ? flags : c->flags;
   hipStream_t s = c->stream;
   if (fill) {
     ProfScope ps(c->prof, s, GRMHD_K_GHOSTS);
@@ -159,38 +162,65 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
   {
     ProfScope ps(c->prof, s, GRMHD_K_UPDATE);
     HIP_OR_FAIL(c, launch_update(c->mixed, c->d, c->t, c->up, c->F[0], c->F[1], c->F[2], Pb, Ps, Pout,
-                                 c->flags, dt, dt_dev, dt_scale, c->ctr, s),
+                                 fl, dt, dt_dev, dt_scale, c->ctr, s),
                 "update");
   }
-  {
+  if (fix) {
     ProfScope ps(c->prof, s, GRMHD_K_FIXUP);
-    HIP_OR_FAIL(c, launch_fixup(c->d, c->t, c->up, Pout, c->flags, c->ctr, s), "fixup");
+    HIP_OR_FAIL(c, launch_fixup(c->d, c->t, c->up, Pout, fl, c->ctr, 0, s), "fixup");
   }
   if (el) {
     ProfScope ps(c->prof, s, GRMHD_K_ELECTRONS);
-    HIP_OR_FAIL(c, launch_electron_heat(c->d, c->t, c->p.gam, Pout, c->Uk, el->Eout, el->model, el->fel, s),
+    HIP_OR_FAIL(c, launch_electron_heat(c->d, c->t, c->p.gam, Pout, c->Uk, el->Eout, el->model, el->fel, c->ctr, s),
                 "electron heating");
   }
   return GRMHD_OK;
 }
 
-int read_speeds(grmhd_ctx* c, double v[3]) {
-  unsigned long long bits[3];
-  HIP_OR_FAIL(c, hipMemcpyAsync(bits, c->ctr->ctop, sizeof(bits), hipMemcpyDeviceToHost, c->stream), "copy ctop");
+// the context's counters on the host; synchronises
+int read_counters(grmhd_ctx* c, Counters* h) {
+  HIP_OR_FAIL(c, hipMemcpyAsync(h, c->ctr, sizeof(Counters), hipMemcpyDeviceToHost, c->stream), "copy counters");
   HIP_OR_FAIL(c, hipStreamSynchronize(c->stream), "synchronize");
-  for (int d = 0; d < 3; ++d) std::memcpy(&v[d], &bits[d], sizeof(double));
+  return GRMHD_OK;
+}
+
+int read_speeds(grmhd_ctx* c, double v[3]) {
+  Counters h;
+  const int st = read_counters(c, &h);
+  if (st != GRMHD_OK) return st;
+  for (int d = 0; d < 3; ++d) std::memcpy(&v[d], &h.ctop[d], sizeof(double));
   for (int d = 0; d < 3; ++d)
     if (!std::isfinite(v[d])) return fail(c, GRMHD_ESTATE, "non-finite signal speed in the state");
   return GRMHD_OK;
+}
+
+// dt = cfl / sum_d (ctop_d / dx_d): the Courant rule of the method, on the host
+double courant_dt(double cfl, const double ctop[3], const double dx[3]) {
+  double sum = 0.0;
+  for (int d = 0; d < 3; ++d) sum += ctop[d] / dx[d];
+  return sum > 0.0 ? cfl / sum : INFINITY;
 }
 
 int read_dt(grmhd_ctx* c, double* dt) {
   double v[3];
   const int st = read_speeds(c, v);
   if (st != GRMHD_OK) return st;
-  double sum = 0.0;
-  for (int d = 0; d < 3; ++d) sum += v[d] / c->dx[d];
-  *dt = sum > 0.0 ? c->p.cfl / sum : INFINITY;
+  *dt = courant_dt(c->p.cfl, v, c->dx);
+  return GRMHD_OK;
+}
+
+// after a step: GRMHD_ESTATE if a non-finite value was stored in the state or
+// a corrector signal speed is not finite; dt_next (nullable) from the speeds
+int finish_step(grmhd_ctx* c, double* dt_next) {
+  Counters h;
+  const int st = read_counters(c, &h);
+  if (st != GRMHD_OK) return st;
+  if (h.bad) return fail(c, GRMHD_ESTATE, "non-finite value in the state after the step");
+  double v[3];
+  for (int d = 0; d < 3; ++d) std::memcpy(&v[d], &h.ctop[d], sizeof(double));
+  for (int d = 0; d < 3; ++d)
+    if (!std::isfinite(v[d])) return fail(c, GRMHD_ESTATE, "non-finite signal speed in the state");
+  if (dt_next) *dt_next = courant_dt(c->p.cfl, v, c->dx);
   return GRMHD_OK;
 }
 
@@ -233,7 +263,7 @@ int run_steps(grmhd_ctx* ctx, double* P, double* E, int32_t model, double fel, i
               "read status");
   HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
   *dt = host.dt;
-  if (host.status) return fail(ctx, GRMHD_ESTATE, "non-finite signal speed in the state");
+  if (host.status) return fail(ctx, GRMHD_ESTATE, "non-finite signal speed or state value");
   return GRMHD_OK;
 }
 
@@ -329,6 +359,7 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
   c->up.floors = p->floors ? 1 : 0;
   c->up.polar_lo = p->bc[1][0] == GRMHD_BC_POLAR;
   c->up.polar_hi = p->bc[1][1] == GRMHD_BC_POLAR;
+  for (int d = 0; d < 3; ++d) c->up.periodic[d] = p->bc[d][0] == GRMHD_BC_PERIODIC;
 
   const size_t ts = (size_t)c->d.ts, sv = (size_t)c->d.sv;
   const size_t fsz = c->mixed ? sizeof(float) : sizeof(double);
@@ -462,7 +493,7 @@ int grmhd_cons_to_prim(grmhd_ctx* ctx, const double* U, double* P, int8_t* flags
   hipStream_t s = ctx->stream;
   HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 4, s), "reset");
   HIP_OR_FAIL(ctx, launch_cons_to_prim(ctx->d, ctx->t, up, U, P, fl, ctx->ctr, s), "cons_to_prim");
-  if (opts & GRMHD_OPT_FIXUP) HIP_OR_FAIL(ctx, launch_fixup(ctx->d, ctx->t, up, P, fl, ctx->ctr, s), "fixup");
+  if (opts & GRMHD_OPT_FIXUP) HIP_OR_FAIL(ctx, launch_fixup(ctx->d, ctx->t, up, P, fl, ctx->ctr, 0, s), "fixup");
   if (n_fail) {
     unsigned int nf = 0;
     HIP_OR_FAIL(ctx, hipMemcpyAsync(&nf, &ctx->ctr->fail, sizeof(nf), hipMemcpyDeviceToHost, s), "copy");
@@ -494,8 +525,7 @@ int grmhd_step(grmhd_ctx* ctx, double* P, double dt, double* dt_next) {
   if (st != GRMHD_OK) return st;
   st = substep(ctx, ctx->Ph, P, P, dt, true);
   if (st != GRMHD_OK) return st;
-  if (dt_next) return read_dt(ctx, dt_next);
-  return GRMHD_OK;
+  return finish_step(ctx, dt_next);
 }
 
 int grmhd_step_electrons(grmhd_ctx* ctx, double* P, double* E, double dt, int32_t model, double fel,
@@ -511,8 +541,7 @@ int grmhd_step_electrons(grmhd_ctx* ctx, double* P, double* E, double dt, int32_
   const ElectronPass corr{ctx->Eh, E, E, model, fel};
   st = substep(ctx, ctx->Ph, P, P, dt, true, nullptr, 1.0, true, &corr);
   if (st != GRMHD_OK) return st;
-  if (dt_next) return read_dt(ctx, dt_next);
-  return GRMHD_OK;
+  return finish_step(ctx, dt_next);
 }
 
 int grmhd_run(grmhd_ctx* ctx, double* P, int32_t nsteps, double* dt) {
@@ -549,9 +578,44 @@ int grmhd_substep(grmhd_ctx* ctx, const double* Ps, const double* Pb, double* Po
                  false);
 }
 
+int grmhd_update(grmhd_ctx* ctx, const double* Ps, const double* Pb, double* Pout, double dt, int32_t want_speeds,
+                 int8_t* flags) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!Ps || !Pb || !Pout || !flags) return fail(ctx, GRMHD_EINVAL, "update: NULL argument");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, GRMHD_EINVAL, "update: dt must be finite and > 0");
+  return substep(ctx, const_cast<double*>(Ps), const_cast<double*>(Pb), Pout, dt, want_speeds != 0, nullptr, 1.0,
+                 false, nullptr, flags, false);
+}
+
+int grmhd_fixup(grmhd_ctx* ctx, double* P, const int8_t* flags, int32_t halo_sides) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !flags) return fail(ctx, GRMHD_EINVAL, "fixup: NULL argument");
+  if (halo_sides & ~63) return fail(ctx, GRMHD_EINVAL, "fixup: halo_sides has bits beyond the six sides");
+  for (int d = 0; d < 3; ++d)
+    if (ctx->up.periodic[d] && ((halo_sides >> (2 * d)) & 3))
+      return fail(ctx, GRMHD_EINVAL, "fixup: a periodic direction cannot have halo sides");
+  ProfScope ps(ctx->prof, ctx->stream, GRMHD_K_FIXUP);
+  HIP_OR_FAIL(ctx, launch_fixup(ctx->d, ctx->t, ctx->up, P, flags, ctx->ctr, halo_sides, ctx->stream), "fixup");
+  return GRMHD_OK;
+}
+
 int grmhd_speeds(grmhd_ctx* ctx, double ctop[3]) {
   if (!ctx || !ctop) return GRMHD_EINVAL;
   return read_speeds(ctx, ctop);
+}
+
+int grmhd_courant_dt(const grmhd_ctx* ctx, const double* ctop, int32_t nparts, double* dt) {
+  if (!ctx || !ctop || !dt || nparts < 1) return GRMHD_EINVAL;
+  double v[3] = {0.0, 0.0, 0.0};
+  for (int q = 0; q < nparts; ++q)
+    for (int d = 0; d < 3; ++d) {
+      const double c = ctop[3 * q + d];
+      if (!std::isfinite(c)) return GRMHD_ESTATE;
+      if (c < 0.0) return GRMHD_EINVAL;
+      v[d] = std::fmax(v[d], c);
+    }
+  *dt = courant_dt(ctx->p.cfl, v, ctx->dx);
+  return GRMHD_OK;
 }
 
 int grmhd_step_failures(grmhd_ctx* ctx, int64_t* n_fail) {

@@ -13,7 +13,7 @@
 
 namespace {
 
-constexpr int GB = 64;  // threads per block of the x2 / x3 ghost fills
+constexpr int GB = 64;           // threads per block of the x2 / x3 ghost fills
 
 __device__ inline int wrap(int x, int n) {
   int r = x % n;
@@ -173,42 +173,51 @@ __global__ __launch_bounds__(256) void scalar_ghost_batch_kernel(BatchView bv, i
   else ghost_x3_body<GRMHD_NSCALAR, true>(J.p, J.d, tgt, src, b);
 }
 
-// corner-centred divergence of sqrt(-g) B; corner (i, j, k) sits at (i-1/2, j-1/2, k-1/2)
+// |corner-centred divergence of sqrt(-g) B| at corner (i, j, k), which sits at
+// (i-1/2, j-1/2, k-1/2); 0 for corners outside the grid or on a non-periodic
+// edge, +inf for a NaN
+__device__ double divb_at(const grmhd_problem& p, const Dims& d, const double* __restrict__ cent,
+                          const double* __restrict__ P, int i, int j, int k) {
+  const bool p1 = p.bc[0][0] == GRMHD_BC_PERIODIC, p2 = p.bc[1][0] == GRMHD_BC_PERIODIC,
+             p3 = p.bc[2][0] == GRMHD_BC_PERIODIC;
+  const bool ok = i < d.n1 && j < d.n2 && k < d.n3 && (p1 || i > 0) && (p2 || j > 0) && (p3 || k > 0);
+  if (!ok) return 0.0;
+  const int im = wrap(i - 1, d.n1), jm = wrap(j - 1, d.n2), km = wrap(k - 1, d.n3);
+  // G_d(kk, jj, ii) = sqrt(-g) B^d
+  auto G = [&](int v, int kk, int jj, int ii) {
+    return cent[T_GDET * d.ts + tab_of(d, jj, ii)] * P[(5 + v) * d.sv + cell_of(d, kk, jj, ii)];
+  };
+  // sum over the two transverse offsets, differencing along the direction
+  const double s1 = (G(0, k, j, i) - G(0, k, j, im)) + (G(0, k, jm, i) - G(0, k, jm, im)) +
+                    (G(0, km, j, i) - G(0, km, j, im)) + (G(0, km, jm, i) - G(0, km, jm, im));
+  const double s2 = (G(1, k, j, i) - G(1, k, jm, i)) + (G(1, k, j, im) - G(1, k, jm, im)) +
+                    (G(1, km, j, i) - G(1, km, jm, i)) + (G(1, km, j, im) - G(1, km, jm, im));
+  const double s3 = (G(2, k, j, i) - G(2, km, j, i)) + (G(2, k, j, im) - G(2, km, j, im)) +
+                    (G(2, k, jm, i) - G(2, km, jm, i)) + (G(2, k, jm, im) - G(2, km, jm, im));
+  const double dx1 = (p.x1max - p.x1min) / p.n1, dx2 = (p.x2max - p.x2min) / p.n2,
+               dx3 = (p.x3max - p.x3min) / p.n3;
+  const double val = fabs(s1 / (4.0 * dx1) + s2 / (4.0 * dx2) + s3 / (4.0 * dx3));
+  return val != val ? __builtin_inf() : val;
+}
+
+// one 64 x 4 block per (x1, x2) tile and x3 plane; the maximum over the block
+// goes into *out by one atomic max
 __global__ void divb_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
                             const double* __restrict__ P, unsigned long long* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  double val = 0.0;
-  const bool p1 = p.bc[0][0] == GRMHD_BC_PERIODIC, p2 = p.bc[1][0] == GRMHD_BC_PERIODIC,
-             p3 = p.bc[2][0] == GRMHD_BC_PERIODIC;
-  const bool ok = i < d.n1 && j < d.n2 && k < d.n3 && (p1 || i > 0) && (p2 || j > 0) && (p3 || k > 0);
-  if (ok) {
-    const int im = wrap(i - 1, d.n1), jm = wrap(j - 1, d.n2), km = wrap(k - 1, d.n3);
-    // G_d(kk, jj, ii) = sqrt(-g) B^d
-    auto G = [&](int v, int kk, int jj, int ii) {
-      return cent[T_GDET * d.ts + tab_of(d, jj, ii)] * P[(5 + v) * d.sv + cell_of(d, kk, jj, ii)];
-    };
-    // sum over the two transverse offsets, differencing along the direction
-    const double s1 = (G(0, k, j, i) - G(0, k, j, im)) + (G(0, k, jm, i) - G(0, k, jm, im)) +
-                      (G(0, km, j, i) - G(0, km, j, im)) + (G(0, km, jm, i) - G(0, km, jm, im));
-    const double s2 = (G(1, k, j, i) - G(1, k, jm, i)) + (G(1, k, j, im) - G(1, k, jm, im)) +
-                      (G(1, km, j, i) - G(1, km, jm, i)) + (G(1, km, j, im) - G(1, km, jm, im));
-    const double s3 = (G(2, k, j, i) - G(2, km, j, i)) + (G(2, k, j, im) - G(2, km, j, im)) +
-                      (G(2, k, jm, i) - G(2, km, jm, i)) + (G(2, k, jm, im) - G(2, km, jm, im));
-    const double dx1 = (p.x1max - p.x1min) / p.n1, dx2 = (p.x2max - p.x2min) / p.n2,
-                 dx3 = (p.x3max - p.x3min) / p.n3;
-    val = fabs(s1 / (4.0 * dx1) + s2 / (4.0 * dx2) + s3 / (4.0 * dx3));
-    if (val != val) val = __builtin_inf();
-  }
-  block_max_to(val, out);
+  block_max_to(divb_at(p, d, cent, P, i, j, (int)blockIdx.z), out);
 }
+
 
 __device__ void reset_counters(Counters* c, int mask) {
   if (mask & 1) c->ctop[0] = c->ctop[1] = c->ctop[2] = 0ull;
   if (mask & 2) c->divb = 0ull;
   if (mask & 4) c->fail = 0u;
-  if (mask & 8) c->fail_total = 0u;
+  if (mask & 8) {
+    c->fail_total = 0u;
+    c->bad = 0u;
+  }
 }
 
 __global__ void reset_kernel(Counters* c, int mask) {
@@ -223,11 +232,13 @@ __global__ void reset_batch_kernel(BatchView bv, int mask) {
 }
 
 // dt <- min(cfl / sum_d (ctop_d / dx_d), 1.3 dt) (1.3 dt when every speed is
-// 0); a non-finite speed keeps dt and raises the status flag. The same
-// operations, in the same order, as the host rule after grmhd_step.
-__device__ void device_dt(const unsigned long long* ctop, const double* dx, double cfl, double* dt, int* status) {
+// 0); a non-finite speed, or a non-finite value stored in the state during the
+// step (bad != 0), keeps dt and raises the status flag. The same operations, in
+// the same order, as the host rule after grmhd_step.
+__device__ void device_dt(const unsigned long long* ctop, unsigned bad, const double* dx, double cfl, double* dt,
+                          int* status) {
   double sum = 0.0;
-  bool finite = true;
+  bool finite = bad == 0u;
   for (int d = 0; d < 3; ++d) {
     const double c = __longlong_as_double((long long)ctop[d]);
     finite = finite && isfinite(c);
@@ -244,7 +255,7 @@ __device__ void device_dt(const unsigned long long* ctop, const double* dx, doub
 __global__ void dt_ctx_kernel(Counters* ctr, double cfl, double dx1, double dx2, double dx3) {
   if (threadIdx.x != 0) return;
   const double dx[3] = {dx1, dx2, dx3};
-  device_dt(ctr->ctop, dx, cfl, &ctr->dt, &ctr->status);
+  device_dt(ctr->ctop, ctr->bad, dx, cfl, &ctr->dt, &ctr->status);
 }
 
 __global__ void dt_batch_kernel(BatchView bv) {
@@ -252,8 +263,10 @@ __global__ void dt_batch_kernel(BatchView bv) {
   if (jb >= bv.njobs) return;
   const JobDesc& J = bv.jobs[jb];
   const double dx[3] = {J.up.dx1, J.up.dx2, J.up.dx3};
-  device_dt(J.ctr->ctop, dx, J.p.cfl, J.dt, J.status);
+  device_dt(J.ctr->ctop, J.ctr->bad, dx, J.p.cfl, J.dt, J.status);
 }
+
+dim3 divb_grid(const Dims& d) { return dim3((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.n3); }
 
 }  // namespace
 
@@ -282,8 +295,7 @@ hipError_t launch_fill_scalar_ghosts(const grmhd_problem& p, const Dims& d, doub
 hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P,
                        Counters* ctr, hipStream_t s) {
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr, 2);
-  hipLaunchKernelGGL(divb_kernel, dim3((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.n3), dim3(64, 4, 1), 0, s, p,
-                     d, t.cent, P, &ctr->divb);
+  hipLaunchKernelGGL(divb_kernel, divb_grid(d), dim3(64, 4, 1), 0, s, p, d, t.cent, P, &ctr->divb);
   return hipGetLastError();
 }
 

@@ -26,9 +26,9 @@
 //             beta_max = 1/(4 sigma_w);
 //   Howes:    theta = T_i/T_e, Q_i/Q_e = 0.92 (c2^2 + beta_i^x)/(c3^2 + beta_i^x)
 //             sqrt(theta m_p/m_e) exp(-1/beta_i), x = 2 - 0.2 log10 theta,
-//             c2 = 1.6/theta, c3 = 18 + 5 log10 theta (theta > 1) else 18,
-//             beta_i^x capped at e^700;
-//   Sharma:   Q_i/Q_e = sqrt(T_i/T_e) / 3 (the ratio commonly quoted from that work);
+//             c2 = 1.6/theta, c3 = 18 + 5 log10 theta for theta > 1,
+//             c2 = 1.2/theta, c3 = 18 otherwise, beta_i^x capped at e^700;
+//   Sharma:   Q_e/Q_i = sqrt(T_e/T_i) / 3, i.e. Q_i/Q_e = 3 sqrt(T_i/T_e);
 // with f_e = 1 / (1 + Q_i/Q_e) where a ratio is given.
 #include "kernels.h"
 
@@ -149,11 +149,11 @@ __device__ double heating_fraction(int model, double fel, double rho, double u, 
     const double x = fmax(1.0 - beta / bmax, 0.0);
     return 0.5 * exp(-pow(x, 3.3) / (1.0 + 1.2 * pow(sw, 0.7)));
   }
-  if (model == GRMHD_HEAT_SHARMA) return 1.0 / (1.0 + sqrt(pi / fmax(pe, 1e-300)) / 3.0);
+  if (model == GRMHD_HEAT_SHARMA) return 1.0 / (1.0 + 3.0 * sqrt(pi / fmax(pe, 1e-300)));
   // Howes
   const double theta = pi / fmax(pe, 1e-300);
   const double lt = log10(theta);
-  const double c2 = 1.6 / theta;
+  const double c2 = (theta > 1.0 ? 1.6 : 1.2) / theta;
   const double c3 = theta > 1.0 ? 18.0 + 5.0 * lt : 18.0;
   const double x = 2.0 - 0.2 * lt;
   const double bx = exp(fmin(x * log(beta), 700.0));
@@ -164,7 +164,7 @@ __device__ double heating_fraction(int model, double fel, double rho, double u, 
 // b: block index within this job's grid
 __device__ void electron_heat_body(const Dims& d, const double* __restrict__ cent, double gam, double* __restrict__ P,
                                    const double* __restrict__ Uk, double* __restrict__ E, int model, double fel,
-                                   int b) {
+                                   unsigned* bad, int b) {
   const TileK tk = xcd_tile_k(b, d.utx, d.uty, d.n1, d.n3);
   const int i = tk.i0 + (int)threadIdx.x;
   const int j = tk.j0 + (int)threadIdx.y;
@@ -193,12 +193,14 @@ __device__ void electron_heat_body(const Dims& d, const double* __restrict__ cen
   kel = fmin(fmax(kel, 0.0), scale * ktot);
   E[c] = ktot;
   E[d.sv + c] = kel;
+  if (!(isfinite(ktot) && isfinite(kel))) atomicAdd(bad, 1u);
 }
 
 __global__ __launch_bounds__(256) void electron_heat_kernel(Dims d, const double* __restrict__ cent, double gam,
                                                             double* __restrict__ P, const double* __restrict__ Uk,
-                                                            double* __restrict__ E, int model, double fel) {
-  electron_heat_body(d, cent, gam, P, Uk, E, model, fel, (int)blockIdx.x);
+                                                            double* __restrict__ E, int model, double fel,
+                                                            Counters* ctr) {
+  electron_heat_body(d, cent, gam, P, Uk, E, model, fel, &ctr->bad, (int)blockIdx.x);
 }
 
 // predictor: heats P_h into E_h; corrector: P into E
@@ -208,7 +210,8 @@ __global__ __launch_bounds__(256) void electron_heat_batch_kernel(BatchView bv, 
   const JobDesc& J = bv.jobs[jb];
   if (!J.E) return;
   electron_heat_body(J.d, global_ptr(J.t.cent), J.p.gam, global_ptr(corrector ? J.P : J.Ph), global_ptr(J.Uk),
-                     global_ptr(corrector ? J.E : J.Eh), J.heat_model, J.fel, (int)blockIdx.x - offs[jb]);
+                     global_ptr(corrector ? J.E : J.Eh), J.heat_model, J.fel, global_ptr(&J.ctr->bad),
+                     (int)blockIdx.x - offs[jb]);
 }
 
 template <typename TF>
@@ -256,8 +259,8 @@ hipError_t launch_batch_electrons(const BatchView& bv, const int* totals, bool m
 }
 
 hipError_t launch_electron_heat(const Dims& d, const Tables& t, double gam, double* P, const double* Uk, double* E,
-                                int model, double fel, hipStream_t s) {
+                                int model, double fel, Counters* ctr, hipStream_t s) {
   const dim3 grid(xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty)), block(d.utx, d.uty, 1);
-  hipLaunchKernelGGL(electron_heat_kernel, grid, block, 0, s, d, t.cent, gam, P, Uk, E, model, fel);
+  hipLaunchKernelGGL(electron_heat_kernel, grid, block, 0, s, d, t.cent, gam, P, Uk, E, model, fel, ctr);
   return hipGetLastError();
 }

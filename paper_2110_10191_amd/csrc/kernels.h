@@ -21,6 +21,7 @@ struct Counters {
   unsigned long long divb;     // max |div B| (double bits)
   unsigned int fail;           // failed inversions of the current substep
   unsigned int fail_total;     // failed inversions since the last reset
+  unsigned int bad;            // non-finite values stored in the state since the last reset
   double dt;                   // step size kept on the device (grmhd_run)
   int status;                  // 1 once a non-finite speed met the device dt rule
 };
@@ -33,6 +34,7 @@ struct UpdateParams {
   double idx1, idx2, idx3;  // 1 / dx_d
   int floors;
   int polar_lo, polar_hi;  // x2 boundaries are polar axes
+  int periodic[3];         // direction d (0 = x1) is periodic
 };
 
 // ---------------------------------------------------------------------------
@@ -132,8 +134,10 @@ hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const Updat
 // ctr->dt <- min(cfl / sum_d(ctop_d / dx_d), 1.3 ctr->dt) on the device
 hipError_t launch_ctx_dt(Counters* ctr, double cfl, double dx1, double dx2, double dx3, hipStream_t s);
 
+// halo: bit 2 d + side set where the ghost layer on that side of direction d
+// holds a neighbouring part's zones (values and failure flags) for the fixup
 hipError_t launch_fixup(const Dims& d, const Tables& t, const UpdateParams& up, double* P,
-                        const int8_t* flags, const Counters* ctr, hipStream_t s);
+                        const int8_t* flags, Counters* ctr, int halo, hipStream_t s);
 
 hipError_t launch_prim_to_cons(const Dims& d, const Tables& t, double gam, const double* P,
                                double* U, hipStream_t s);
@@ -144,6 +148,7 @@ hipError_t launch_cons_to_prim(const Dims& d, const Tables& t, const UpdateParam
 
 hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P,
                        Counters* ctr, hipStream_t s);
+
 
 // electron heating: the ghost zones of the two entropies (the primitives'
 // rules without the axis sign change and the inflow fix); the advection of
@@ -157,7 +162,7 @@ hipError_t launch_scalar_advect(bool mixed, int recon, const Dims& d, const Tabl
                                 const double* Es, double* Uk, double dt, const double* dt_dev, double dt_scale,
                                 hipStream_t s);
 hipError_t launch_electron_heat(const Dims& d, const Tables& t, double gam, double* P, const double* Uk, double* E,
-                                int model, double fel, hipStream_t s);
+                                int model, double fel, Counters* ctr, hipStream_t s);
 
-// zero the counters selected by mask (1: ctop, 2: divb, 4: fail, 8: fail_total)
+// zero the counters selected by mask (1: ctop, 2: divb, 4: fail, 8: fail_total and bad)
 hipError_t launch_reset(Counters* ctr, int mask, hipStream_t s);

@@ -74,8 +74,11 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
     const T cmax = fmax(fmax(T(0), cpL), cpR);
     const T cmin = fmax(fmax(T(0), -cmL), -cmR);
     const T ct = fmax(cmax, cmin);
+    // the flux of the face-normal field component (v = 4 + D) is not stored:
+    // Flux-CT replaces it by zero, and nothing else reads it
 #pragma unroll
-    for (int v = 0; v < NV; ++v) F[v * d.sv + c] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * ct * (UR[v] - UL[v]);
+    for (int v = 0; v < NV; ++v)
+      if (v != 4 + D) F[v * d.sv + c] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * ct * (UR[v] - UL[v]);
     bool inner;
     if (D == 1) inner = (j >= 0 && j < d.n2 && k >= 0 && k < d.n3);
     else if (D == 2) inner = (i >= 0 && i < d.n1 && k >= 0 && k < d.n3);

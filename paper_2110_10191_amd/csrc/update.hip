@@ -254,6 +254,11 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
 #pragma unroll
     for (int v = 0; v < NV; ++v) Pout[v * d.sv + c] = pn[v];
     flags[c] = (int8_t)failed;
+    // Non-finite values left in the state. The hydro primitives of a zone
+    // whose inversion succeeded are finite (a non-finite result is a failure,
+    // and the bounds only take maxima with finite floors), and a failed zone's
+    // are the fixup's to check: only the field can carry one out of here.
+    if (!(isfinite(pn[5]) && isfinite(pn[6]) && isfinite(pn[7]))) atomicAdd(&ctr->bad, 1u);
   }
   block_count_to(failed, &ctr->fail, &ctr->fail_total);
 }
@@ -289,10 +294,23 @@ __global__ __launch_bounds__(256, 3) void update_batch_kernel(BatchView bv, int 
                   (int)blockIdx.x - offs[jb]);
 }
 
-// failed zone <- mean of the hydro primitives of its non-failed interior
-// neighbours among the 26 (values before any repair), then the bounds
+// neighbour index along one direction for the fixup: across a periodic
+// direction the zone on the other side of the seam, across a side whose ghost
+// layer holds a neighbouring part's zones (halo bit) the ghost zone, else none
+__device__ inline bool fixup_neighbour(int& x, int n, bool periodic, int halo, int lo_bit) {
+  if (x >= 0 && x < n) return true;
+  if (periodic) {
+    x = x < 0 ? x + n : x - n;
+    return true;
+  }
+  return (halo >> (lo_bit + (x < 0 ? 0 : 1))) & 1;
+}
+
+// failed zone <- mean of the hydro primitives of its non-failed neighbours
+// among the 26 (values before any repair; across periodic directions and
+// part boundaries as fixup_neighbour says), then the bounds
 __device__ void fixup_body(const Dims& d, const double* __restrict__ cent, const UpdateParams& up, double* P,
-                           const int8_t* __restrict__ flags, const Counters* ctr, int b) {
+                           const int8_t* __restrict__ flags, Counters* ctr, int halo, int b) {
   if (ctr->fail == 0u) return;
   const TileK tk = xcd_tile_k(b, d.utx, d.uty, d.n1, d.n3);
   const int i = tk.i0 + (int)threadIdx.x;
@@ -307,8 +325,11 @@ __device__ void fixup_body(const Dims& d, const double* __restrict__ cent, const
     for (int dj = -1; dj <= 1; ++dj)
       for (int di = -1; di <= 1; ++di) {
         if (dk == 0 && dj == 0 && di == 0) continue;
-        const int kk = k + dk, jj = j + dj, ii = i + di;
-        if (kk < 0 || kk >= d.n3 || jj < 0 || jj >= d.n2 || ii < 0 || ii >= d.n1) continue;
+        int kk = k + dk, jj = j + dj, ii = i + di;
+        if (!fixup_neighbour(ii, d.n1, up.periodic[0], halo, 0) ||
+            !fixup_neighbour(jj, d.n2, up.periodic[1], halo, 2) ||
+            !fixup_neighbour(kk, d.n3, up.periodic[2], halo, 4))
+          continue;
         const int cc = cell_of(d, kk, jj, ii);
         if (flags[cc]) continue;
         for (int v = 0; v < 5; ++v) acc[v] += P[v * d.sv + cc];
@@ -324,13 +345,18 @@ __device__ void fixup_body(const Dims& d, const double* __restrict__ cent, const
     load_geo(g, cent, d.ts, toff);
     apply_floors(pn, g, cent[T_RHOFL * d.ts + toff], cent[T_UFL * d.ts + toff], up);
   }
-  for (int v = 0; v < 5; ++v) P[v * d.sv + c] = pn[v];
+  bool fin = true;
+  for (int v = 0; v < 5; ++v) {
+    P[v * d.sv + c] = pn[v];
+    fin = fin && isfinite(pn[v]);
+  }
+  if (!fin) atomicAdd(&ctr->bad, 1u);
 }
 
 __global__ __launch_bounds__(256) void fixup_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
-                                                    double* P, const int8_t* __restrict__ flags,
-                                                    const Counters* ctr) {
-  fixup_body(d, cent, up, P, flags, ctr, (int)blockIdx.x);
+                                                    double* P, const int8_t* __restrict__ flags, Counters* ctr,
+                                                    int halo) {
+  fixup_body(d, cent, up, P, flags, ctr, halo, (int)blockIdx.x);
 }
 
 __global__ __launch_bounds__(256) void fixup_batch_kernel(BatchView bv, int corrector) {
@@ -338,7 +364,7 @@ __global__ __launch_bounds__(256) void fixup_batch_kernel(BatchView bv, int corr
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
   fixup_body(J.d, global_ptr(J.t.cent), J.up, global_ptr(corrector ? J.P : J.Ph), global_ptr(J.flags),
-             global_ptr(J.ctr), (int)blockIdx.x - offs[jb]);
+             global_ptr(J.ctr), 0, (int)blockIdx.x - offs[jb]);
 }
 
 __global__ __launch_bounds__(256) void p2u_kernel(Dims d, const double* __restrict__ cent, double gam,
@@ -412,9 +438,9 @@ hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const Updat
 }
 
 hipError_t launch_fixup(const Dims& d, const Tables& t, const UpdateParams& up, double* P, const int8_t* flags,
-                        const Counters* ctr, hipStream_t s) {
+                        Counters* ctr, int halo, hipStream_t s) {
   const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
-  hipLaunchKernelGGL(fixup_kernel, dim3(nblk), dim3(d.utx, d.uty, 1), 0, s, d, t.cent, up, P, flags, ctr);
+  hipLaunchKernelGGL(fixup_kernel, dim3(nblk), dim3(d.utx, d.uty, 1), 0, s, d, t.cent, up, P, flags, ctr, halo);
   return hipGetLastError();
 }
 

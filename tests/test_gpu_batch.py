@@ -206,6 +206,34 @@ def test_a_non_finite_zone_in_one_job_leaves_the_others_untouched(lib, var):
         assert dts[2] == dt0[2]
 
 
+@pytest.mark.parametrize("var,bad", [(5, True), (7, True), (1, False)], ids=["nan_B1", "nan_B3", "nan_u"])
+def test_step_reports_a_non_finite_state_without_dt_next(lib, var, bad):
+    """grmhd_step with dt_next = NULL: a NaN field component stays in the state
+    and the step returns GRMHD_ESTATE; a NaN internal energy is repaired by the
+    fixup and the step succeeds. The same for the electron step and grmhd_run."""
+    prm, P0 = problems.fm_torus(n1=48, n2=28, n3=4)
+    for call in ("step", "step_electrons", "run"):
+        sim = lib.Sim(prm)
+        P = sim.to_device(P0)
+        E = sim.to_device(problems.electron_scalars(P0, prm["gam"], te_ti=1.0))
+        dt = sim.get_dt(P)
+        P[var, NG + 1, NG + 5, NG + 10] = float("nan")
+        if call == "step":
+            f = lambda: sim.step(P, dt, want_dt_next=False)
+        elif call == "step_electrons":
+            f = lambda: sim.step_electrons(P, E, dt, "constant", 0.5, want_dt_next=False)
+        else:
+            f = lambda: sim.run(P, 2, dt)
+        if bad:
+            with pytest.raises(lib.GrmhdError) as e:
+                f()
+            assert e.value.status == lib.GRMHD_ESTATE, call
+        else:
+            f()
+            assert np.isfinite(interior(sim.to_host(P), prm)).all(), call
+        sim.close()
+
+
 def test_a_non_finite_state_is_an_error_of_the_step(lib):
     prm, P0 = problems.fm_torus(n1=48, n2=28, n3=4)
     sim = lib.Sim(prm)
