@@ -15,11 +15,18 @@ steps go through grmhd_run, which keeps the step size on the device so the
 host does not wait between steps (``--path host`` calls grmhd_step once a
 step and reads dt back each time; the two give identical states). The metric is
 zone-cycles per second: interior zones x steps / wall seconds over the timed
-steps (bracketed by device synchronisation). Kernel durations over the same
-timed region come from HIP events the library records on its stream around
-every launch; the dominant kernel's algorithmic bytes per launch over its mean
-duration give the roofline fraction against 8 TB/s. The oracle (NumPy FP64,
-one core) is timed on a bounded sample of the same workload.
+steps (bracketed by device synchronisation), which run as 5 consecutive
+repeats whose median rate is reported beside the total. Kernel durations over
+the same timed region come from HIP events the library records on its stream
+around every launch. The roofline fraction is the dominant kernel's
+algorithmic bytes per launch over its mean duration against 8 TB/s, where the
+algorithmic bytes are the method's compulsory bytes (the P^n, P_h, P^n+1
+state traffic of a step plus the 2D geometry, 338.75 B per zone-cycle on the
+benchmark torus) for the zone-cycles one launch advances; this design's own
+byte model (face fluxes included) is a separate view. The line also carries a
+few steps of the 64-job batched workload against the per-job FP64 loop
+(``many``), and the oracle (NumPy FP64, one core) timed on a bounded sample of
+the same torus.
 
 Prints one JSON line on stdout.
 """
@@ -39,10 +46,22 @@ FP32_PEAK = 157.3e12       # flop/s, MI355X FP32 vector
 NG = 3
 
 
-def algorithmic_bytes(kernel, prm, mixed):
-    """Bytes one launch must move at minimum: every input value read once and
-    every output written once (stencil re-reads are cache traffic, not algorithm).
-    """
+def compulsory_bytes_per_zone_cycle(prm):
+    """The method's compulsory HBM bytes per zone-cycle with an FP64 state: a
+    step reads P^n and writes P_h (predictor), reads P^n and P_h and writes
+    P^{n+1} (corrector), 5 x 64 = 320 B a zone; plus, on a Kerr grid, the
+    axisymmetric geometry, about 150 doubles per (x1, x2) column per substep,
+    shared by the n3 zones of the column. 338.75 B on the 288 x 128 x 128 torus."""
+    geo = 0.0 if prm["coords"] == 0 else 2 * 150 * 8 / prm["n3"]
+    return 320.0 + geo
+
+
+def split_design_bytes(kernel, prm, mixed):
+    """Bytes one launch of this split design moves at minimum: every value it
+    reads once and every value it writes once (stencil re-reads are cache
+    traffic), including the face fluxes the sweeps write and the update reads
+    back. A view of the design, not of the method: the method's compulsory
+    bytes are compulsory_bytes_per_zone_cycle."""
     n1, n2, n3 = prm["n1"], prm["n2"], prm["n3"]
     fb = 4 if mixed else 8
     recon_reach = 3 if prm["recon"] == 1 else 2          # zones below / above+1 a face
@@ -59,7 +78,7 @@ def algorithmic_bytes(kernel, prm, mixed):
                 faces *= n[e] + 2
                 cells *= n[e] + 2
         geo = 22 * fb * (n1 + 2) * (n2 + 2)
-        return 64 * cells + 8 * fb * faces + geo
+        return 64 * cells + 7 * fb * faces + geo
     if kernel == "update":
         zones = n1 * n2 * n3
         # 7 flux components per direction (5 hydro + 2 transverse B); the states
@@ -91,18 +110,18 @@ def device_copy_bandwidth(torch, dev, gib=1.0, reps=5):
     return 2 * nel * 8 / best
 
 
-def measured_traffic(kernel, workload):
-    """HBM bytes per launch of ``kernel`` from the committed counter summary
-    (profiles/hbm_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a plain
-    copy), only while the library is the build those counters were taken on."""
+def measured_traffic(workload):
+    """HBM bytes per launch of each kernel class from the committed counter
+    summary (profiles/hbm_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a
+    plain copy), with launches per step, only while the library is the build
+    those counters were taken on."""
     path = os.path.join(HERE, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
         from paper_2110_10191_amd import tune
-        if (rec.get("kernel") == kernel and rec.get("workload") == workload
-                and rec.get("library_hash") == tune.library_hash()):
-            return float(rec["bytes_per_launch"])
+        if rec.get("workload") == workload and rec.get("library_hash") == tune.library_hash():
+            return rec["kernels"]
     except (OSError, ValueError, KeyError):
         pass
     return None
@@ -138,10 +157,21 @@ def cpu_baseline(prm_full, nslabs=32, nsteps=2):
         P, _, _ = oracle.step(P, g, dt)
     secs = time.perf_counter() - t0
     zones = prm["n1"] * prm["n2"] * prm["n3"]
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": zones * nsteps / secs,
         "unit": "zone-cycles/s",
         "cores": 1,
+        "host_cpu": model,
+        "host_os_cpu_count": os.cpu_count(),
         "kind": "oracle",
         "sample": (f"{nsteps} FP64 steps of the {prm['n1']}x{prm['n2']} FMKS torus grid with {nslabs} x3 slabs "
                    f"({zones} zones, same per-zone work as the benchmark grid) in {secs:.1f} s; "
@@ -149,13 +179,14 @@ def cpu_baseline(prm_full, nslabs=32, nsteps=2):
     }
 
 
-def bench_many(args):
+def many_record(steps, warmup, tune_tiles):
     """64 independent uneven jobs (32 periodic boxes N^3, N in 32..96; 32 Bondi
     flows in Kerr, a ~ U[0, 0.99], up to 192 x 128 x 64): every job advanced
     by the batch calls (one grid per kernel phase over all jobs, a captured
     HIP graph per step, per-job dt on the device), in FP64 and in mixed
-    precision, against the plain loop that steps one job after another in
-    FP64 with a host-side dt per step."""
+    precision, against the plain per-job FP64 loop: one job after another,
+    each through grmhd_run (its step size kept on the device, one host
+    synchronisation per job)."""
     import torch
     import paper_2110_10191_amd as g
     from paper_2110_10191_amd import tune
@@ -166,76 +197,88 @@ def bench_many(args):
     zones = sum(s.zones for s in specs)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    init = [sp.make(recon=problems.RECON_MC, precision=problems.FP64) for sp in specs]
+    print(f"[bench] many: {len(specs)} jobs, {zones} zones of initial data in "
+          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
     res = {}
     for prec_name, prec in (("fp64", problems.FP64), ("mixed", problems.MIXED)):
-        t_gen = time.perf_counter()
         sims, states = [], []
-        for sp in specs:
-            prm, P0 = sp.make(recon=problems.RECON_MC, precision=prec)
-            sim = g.Sim(prm, device=dev)
+        for prm, P0 in init:
+            sim = g.Sim(dict(prm, precision=prec), device=dev)
             sims.append(sim)
             states.append(sim.to_device(P0))
         torch.cuda.synchronize()
-        print(f"[bench] {prec_name}: {len(specs)} jobs, {zones} zones set up in "
-              f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
         tiles = None
-        if args.tune:
+        if tune_tiles:
+            t_tune = time.perf_counter()
             tiles, _ = tune.tune_batch(sims, states, steps=2, repeats=1)
-            print(f"[bench] {prec_name}: batch tiles {tiles}", file=sys.stderr, flush=True)
+            print(f"[bench] many {prec_name}: batch tiles {tiles} ({time.perf_counter() - t_tune:.1f} s)",
+                  file=sys.stderr, flush=True)
         dts = [s.get_dt(P) for s, P in zip(sims, states)]
         b = g.Batch(sims)
         b.set_dt(dts)
-        b.step(states, nsteps=args.warmup)
+        b.step(states, nsteps=warmup)
         b.get()
         t0 = time.perf_counter()
-        b.step(states, nsteps=args.steps)
+        b.step(states, nsteps=steps)
         _, status = b.get()
         secs = time.perf_counter() - t0
         b.close()
-        res[f"batched_{prec_name}"] = {"value": zones * args.steps / secs, "ms_per_step": secs / args.steps * 1e3,
+        res[f"batched_{prec_name}"] = {"value": zones * steps / secs, "ms_per_step": secs / steps * 1e3,
                                        "tiles": tiles, "bad_jobs": int(sum(status))}
-        print(f"[bench] batched {prec_name}: {zones * args.steps / secs:.3e} zone-cycles/s",
+        print(f"[bench] many batched {prec_name}: {zones * steps / secs:.3e} zone-cycles/s",
               file=sys.stderr, flush=True)
         if prec == problems.FP64:
+            # the loop keeps each job's own default tiles (tuning applies to the batch)
+            for s in sims:
+                s.set_tiles("sweep", *tune.DEFAULT["sweep"])
+                s.set_tiles("update", *tune.DEFAULT["update"])
             dts = [s.get_dt(P) for s, P in zip(sims, states)]
-            for s, P, dt in zip(sims, states, dts):
-                s.step(P, dt)                        # warm each job's code path
+            dts = [s.run(P, 1, dt) for s, P, dt in zip(sims, states, dts)]    # warm each job's code path
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             for s, P, dt in zip(sims, states, dts):
-                for _ in range(args.steps):
-                    dt = min(s.step(P, dt), 1.3 * dt)
+                s.run(P, steps, dt)
             torch.cuda.synchronize()
             secs = time.perf_counter() - t0
-            res["per_job_loop_fp64"] = {"value": zones * args.steps / secs,
-                                        "ms_per_step": secs / args.steps * 1e3}
-            print(f"[bench] per-job FP64 loop: {zones * args.steps / secs:.3e} zone-cycles/s",
+            res["per_job_loop_fp64"] = {"value": zones * steps / secs, "ms_per_step": secs / steps * 1e3,
+                                        "driver": "grmhd_run per job"}
+            print(f"[bench] many per-job FP64 loop: {zones * steps / secs:.3e} zone-cycles/s",
                   file=sys.stderr, flush=True)
         for s in sims:
             s.close()
         del states
         torch.cuda.empty_cache()
     base = res["per_job_loop_fp64"]["value"]
-    out = {
-        "metric": "zone-cycles/s, batched uneven jobs vs the per-job FP64 loop",
-        "value": res["batched_mixed"]["value"],
-        "unit": "zone-cycles/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": res["batched_mixed"]["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": "64 uneven jobs: 32 boxes N^3 (N in 32..96), 32 Kerr Bondi (up to 192x128x64), MC",
-                   "zones": zones, "seed": 3},
+    return {
+        "workload": "64 uneven jobs: 32 boxes N^3 (N in 32..96), 32 Kerr Bondi (up to 192x128x64), MC, seed 3",
+        "zones": zones, "steps": steps, "warmup": warmup,
         "batched_fp64": res["batched_fp64"],
         "batched_mixed": res["batched_mixed"],
         "per_job_loop_fp64": res["per_job_loop_fp64"],
         "speedup_batched_mixed_vs_loop": res["batched_mixed"]["value"] / base,
         "speedup_batched_fp64_vs_loop": res["batched_fp64"]["value"] / base,
+    }
+
+
+def bench_many(args):
+    rec = many_record(args.steps, args.warmup, args.tune)
+    out = {
+        "metric": "zone-cycles/s, batched uneven jobs vs the per-job FP64 loop",
+        "value": rec["batched_mixed"]["value"],
+        "unit": "zone-cycles/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": rec["batched_mixed"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": rec["workload"], "zones": rec["zones"], "seed": 3},
+        "many": rec,
     }
     print(json.dumps(out), flush=True)
 
@@ -249,6 +292,9 @@ def main():
     ap.add_argument("--recon", choices=["mc", "weno5"], default="mc")
     ap.add_argument("--grid", type=int, nargs=3, default=[288, 128, 128])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-many", action="store_true",
+                    help="leave out the 64-job batched-vs-loop sub-record of the torus line")
+    ap.add_argument("--many-steps", type=int, default=5, help="timed steps of the 64-job sub-record")
     ap.add_argument("--workload", choices=["torus", "many"], default="torus",
                     help="torus: one large torus (default); many: 64 uneven jobs batched vs looped")
     ap.add_argument("--tune", action="store_true", help="autotune the batch tiles (workload many)")
@@ -291,70 +337,45 @@ def main():
     torch.cuda.synchronize()
 
     dt = sim.get_dt(P)
-    kernels = {}
-    if args.electrons and args.path == "device":
-        # the fluid step plus the three electron passes per substep, through
-        # grmhd_run_electrons (the step size kept on the device)
+    E = None
+    if args.electrons:
         E = sim.to_device(problems.electron_scalars(P0, prm["gam"]))
-        dt = sim.run_electrons(P, E, args.warmup, dt, args.electrons)
-        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
-        g.grmhd_profile(sim.ctx, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        dt = sim.run_electrons(P, E, args.steps, dt, args.electrons)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        g.grmhd_profile(sim.ctx, False)
-        for name in g.KERNELS:
-            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
-    elif args.electrons:
-        # one grmhd_step_electrons call per step, dt read back every step
-        E = sim.to_device(problems.electron_scalars(P0, prm["gam"]))
-        for _ in range(args.warmup):
-            dt = min(sim.step_electrons(P, E, dt, args.electrons), 1.3 * dt)
-        torch.cuda.synchronize()
-        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
-        g.grmhd_profile(sim.ctx, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            dt = min(sim.step_electrons(P, E, dt, args.electrons), 1.3 * dt)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        g.grmhd_profile(sim.ctx, False)
-        for name in g.KERNELS:
-            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
-    elif args.path == "host":
-        # one grmhd_step call per step; dt read back to the host every step
-        for _ in range(args.warmup):
-            dt = min(sim.step(P, dt), 1.3 * dt)
-        torch.cuda.synchronize()
-        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
-        g.grmhd_profile(sim.ctx, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            dt = min(sim.step(P, dt), 1.3 * dt)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        g.grmhd_profile(sim.ctx, False)
-        for name in g.KERNELS:
-            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
-    else:
-        # grmhd_run: the same kernels with the step size kept on the device
-        # (dt <- min(dt_next, 1.3 dt) by a one-thread kernel), so the host
-        # never waits between steps; every launch is bracketed by events
-        dt = sim.run(P, args.warmup, dt)
-        print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
-        g.grmhd_profile(sim.ctx, True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        dt = sim.run(P, args.steps, dt)
-        torch.cuda.synchronize()
-        secs = time.perf_counter() - t0
-        g.grmhd_profile(sim.ctx, False)
-        for name in g.KERNELS:
-            kernels[name] = g.grmhd_profile_read(sim.ctx, name)
+
+    def advance(nsteps, dt):
+        """nsteps steps through the chosen driver; returns the next dt. Every
+        driver synchronises the host with the device when it returns."""
+        if args.path == "device":
+            # grmhd_run(_electrons): the step size kept on the device (dt <-
+            # min(dt_next, 1.3 dt) by a one-thread kernel); one sync at the end
+            if E is not None:
+                return sim.run_electrons(P, E, nsteps, dt, args.electrons)
+            return sim.run(P, nsteps, dt)
+        # one grmhd_step(_electrons) call per step, dt read back every step
+        for _ in range(nsteps):
+            dn = sim.step_electrons(P, E, dt, args.electrons) if E is not None else sim.step(P, dt)
+            dt = min(dn, 1.3 * dt)
+        return dt
+
+    dt = advance(args.warmup, dt)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done, dt = {dt:.3e}", file=sys.stderr, flush=True)
+    # exactly args.steps timed steps, in 5 consecutive repeats (or fewer when
+    # there are fewer steps) so the median repeat rate comes with the total;
+    # every launch is bracketed by library events on its stream
+    nrep = min(5, args.steps)
+    reps = [args.steps // nrep + (1 if r < args.steps % nrep else 0) for r in range(nrep)]
+    g.grmhd_profile(sim.ctx, True)
+    torch.cuda.synchronize()
+    rep_rates = []
+    t0 = time.perf_counter()
+    for nr in reps:
+        tr = time.perf_counter()
+        dt = advance(nr, dt)
+        rep_rates.append(n1 * n2 * n3 * nr / (time.perf_counter() - tr))
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    g.grmhd_profile(sim.ctx, False)
+    kernels = {name: g.grmhd_profile_read(sim.ctx, name) for name in g.KERNELS}
     fails = sim.step_failures()
     divb = sim.divb(P)
     zones = n1 * n2 * n3
@@ -362,17 +383,35 @@ def main():
     print("[bench] kernel ms/launch: " + ", ".join(
         f"{k} {ms / max(n, 1):.3f}" for k, (ms, n) in kernels.items()), file=sys.stderr, flush=True)
 
+    # roofline of the dominant kernel (the fused update: CT, source, U(P),
+    # inversion, bounds; one launch per substep = Z/2 zone-cycles) with the
+    # method's compulsory bytes per zone-cycle as the algorithmic bytes
     dom = max(("sweep1", "sweep2", "sweep3", "update"), key=lambda k: kernels[k][0])
     ms, n = kernels[dom]
-    per_launch = algorithmic_bytes(dom, prm, mixed)
-    achieved = per_launch / (ms / n / 1e3)
+    t_launch = ms / n / 1e3
+    per_zc = compulsory_bytes_per_zone_cycle(prm)
+    per_launch = per_zc * zones / 2
+    achieved = per_launch / t_launch
     workload = f"fm_torus_{n1}x{n2}x{n3}_{args.recon}_{args.precision}"
     if args.electrons:
         workload += f"_electrons_{args.electrons}"
+    traffic = measured_traffic(workload)
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": measured_traffic(dom, workload),
-                "traffic_unit": "bytes per launch", "kernel": dom,
-                "algorithmic_bytes_per_launch": per_launch, "mean_launch_ms": ms / n}
+                "frac": achieved / HBM_PEAK,
+                "traffic": traffic[dom]["bytes_per_launch"] if traffic and dom in traffic else None,
+                "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                "kernel": dom, "mean_launch_ms": ms / n,
+                "algorithmic_bytes_per_launch": per_launch,
+                "algorithmic_basis": (f"{per_zc:.2f} B per zone-cycle (P^n, P_h, P^n+1 traffic of the two substeps "
+                                      f"plus the 2D geometry over n3) x {zones} zones / 2 (one substep)")}
+    if traffic:
+        step_traffic = sum(rec["bytes_per_launch"] * rec["launches_per_step"] for rec in traffic.values())
+        roofline["traffic_ratio"] = {
+            "per_launch": roofline["traffic"] / per_launch if roofline["traffic"] else None,
+            "per_step": step_traffic / (per_zc * zones),
+            "step_traffic_bytes": step_traffic}
+    else:
+        roofline["traffic_ratio"] = None
 
     if args.copy_calibration_gib > 0:
         nel = int(args.copy_calibration_gib * 2 ** 30) // 8
@@ -382,20 +421,21 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    # the other two views of the HBM roofline: the whole step's compulsory
-    # state traffic (read P^n, write P_h; read P^n and P_h, write P^{n+1}:
-    # 320 B a zone, plus the 2D geometry once per step) at the measured rate,
-    # and the dominant kernel's measured HBM bytes over its time; both against
-    # the nominal peak and against a plain device copy measured here
+    # other views: the whole step's compulsory bytes at the measured step
+    # rate; this split design's own per-launch byte model (face fluxes
+    # included); measured bytes over time; against the nominal peak and a
+    # plain device copy measured here
     copy_bw = device_copy_bandwidth(torch, dev)
-    step_bytes = 320.0 * zones + 2 * 150 * 8 * n1 * n2
+    split = split_design_bytes(dom, prm, mixed)
     views = {"copy_GBps": copy_bw / 1e9,
-             "step_compulsory_bytes_per_zone_cycle": step_bytes / zones,
-             "step_compulsory_frac": value * step_bytes / zones / HBM_PEAK,
-             "step_compulsory_frac_of_copy": value * step_bytes / zones / copy_bw}
+             "step_compulsory_bytes_per_zone_cycle": per_zc,
+             "step_compulsory_frac": value * per_zc / HBM_PEAK,
+             "step_compulsory_frac_of_copy": value * per_zc / copy_bw,
+             "split_design_bytes_per_launch": split,
+             "split_design_frac": split / t_launch / HBM_PEAK}
     if roofline["traffic"]:
-        views["measured_frac"] = roofline["traffic"] / (ms / n / 1e3) / HBM_PEAK
-        views["measured_frac_of_copy"] = roofline["traffic"] / (ms / n / 1e3) / copy_bw
+        views["measured_frac"] = roofline["traffic"] / t_launch / HBM_PEAK
+        views["measured_frac_of_copy"] = roofline["traffic"] / t_launch / copy_bw
     # the VALU view: counted FP64 / FP32 flops per launch over the live mean
     # launch time, against the vector peaks
     flops = measured_flops(workload)
@@ -440,14 +480,22 @@ def main():
                    "precision": args.precision, "coords": "fmks", "r_out": 1000.0,
                    "driver": args.path,
                    "electrons": args.electrons},
+        "repeats": {"n": nrep, "steps": reps, "zone_cycles_per_s": rep_rates,
+                    "median": sorted(rep_rates)[len(rep_rates) // 2]},
         "roofline": roofline,
         "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kernels.items()},
         "checks": {"max_divb": divb, "failed_inversions_last_step": fails, "dt": dt},
     }
+    sim.close()
+    del P
+    torch.cuda.empty_cache()
+    if not args.no_many and not args.electrons:
+        # the batched form against the per-job FP64 loop, a few steps of the
+        # 64-job mix with tuned batch tiles
+        out["many"] = many_record(args.many_steps, 1, True)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prm)
-    sim.close()
     print(json.dumps(out), flush=True)
 
 
