@@ -297,28 +297,6 @@ __device__ inline void block_max_to(double v, unsigned long long* dst) {
   }
 }
 
-// block sums of two counts a, b < 2^15 per block (packed into one int for a
-// single reduction), then one atomic add of each nonzero sum: a into dst_a
-// (and dst_a2), b into dst_b
-__device__ inline void block_count2_to(int a, int b, unsigned int* dst_a, unsigned int* dst_a2, unsigned int* dst_b) {
-  __shared__ int cpart2[16];
-  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
-  const int nthr = blockDim.x * blockDim.y * blockDim.z;
-  int v = wave_sum(a + (b << 16));
-  if ((tid & 63) == 0) cpart2[tid >> 6] = v;
-  __syncthreads();
-  if (tid == 0) {
-    int s = 0;
-    for (int w = 0; w < (nthr + 63) / 64; ++w) s += cpart2[w];
-    const unsigned sa = (unsigned)s & 0xffffu, sb = (unsigned)s >> 16;
-    if (sa) {
-      atomicAdd(dst_a, sa);
-      atomicAdd(dst_a2, sa);
-    }
-    if (sb) atomicAdd(dst_b, sb);
-  }
-}
-
 // block sum of v, then one atomic add into dst (and into dst2 when given)
 __device__ inline void block_count_to(int v, unsigned int* dst, unsigned int* dst2 = nullptr) {
   __shared__ int cpart[16];
