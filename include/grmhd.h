@@ -253,6 +253,19 @@ GRMHD_API int grmhd_run_electrons(grmhd_ctx *ctx, double *P, double *E, int32_t 
  * max_divb (host) is written; synchronises. */
 GRMHD_API int grmhd_divb(grmhd_ctx *ctx, const double *P, double *max_divb);
 
+/* grmhd_divb for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same value as grmhd_divb, bit for bit, but its per-block partial maxima live
+ * in a static device array of the library (65536 slots of 8 bytes plus the
+ * result, 512 KiB, one copy per device, held until the process ends) instead
+ * of the context's scratch; the call allocates nothing. Every call on a device
+ * shares that device's array: calls that overlap on one device (several
+ * streams or host threads) race and must be serialised by the caller. The
+ * grid must need at most 65536 slots, ceil(n1/64) * ceil(n2/4) * n3 <= 65536
+ * (the 288 x 128 x 128 torus needs 20480), else EINVAL. max_divb (host) is
+ * written; synchronises. Errors: EINVAL, EDEVICE. */
+GRMHD_API int grmhd_divb_noalloc(grmhd_ctx *ctx, const double *P, double *max_divb);
+
 /* Failed-inversion count of the last step taken by grmhd_step or grmhd_run
  * (both substeps); synchronises. */
 GRMHD_API int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);

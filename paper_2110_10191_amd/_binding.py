@@ -14,7 +14,7 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 # every symbol include/grmhd.h declares
 EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
-    "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_update", "grmhd_fixup", "grmhd_speeds", "grmhd_courant_dt", "grmhd_divb", "grmhd_step_failures", "grmhd_strerror",
+    "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_update", "grmhd_fixup", "grmhd_speeds", "grmhd_courant_dt", "grmhd_divb", "grmhd_divb_noalloc", "grmhd_step_failures", "grmhd_strerror",
     "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step", "grmhd_batch_step_electrons",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
@@ -91,6 +91,7 @@ def _load():
         "grmhd_fixup": ([vp, vp, vp, i32], ctypes.c_int),
         "grmhd_courant_dt": ([vp, dp, i32, dp], ctypes.c_int),
         "grmhd_divb": ([vp, vp, dp], ctypes.c_int),
+        "grmhd_divb_noalloc": ([vp, vp, dp], ctypes.c_int),
         "grmhd_step_failures": ([vp, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "grmhd_last_error": ([vp], ctypes.c_char_p),
@@ -256,6 +257,12 @@ def grmhd_courant_dt(ctx, speeds):
 def grmhd_divb(ctx, P):
     v = ctypes.c_double()
     _check(lib.grmhd_divb(ctx, _ptr(P), ctypes.byref(v)), ctx)
+    return v.value
+
+
+def grmhd_divb_noalloc(ctx, P):
+    v = ctypes.c_double()
+    _check(lib.grmhd_divb_noalloc(ctx, _ptr(P), ctypes.byref(v)), ctx)
     return v.value
 
 

@@ -342,6 +342,13 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
   c->stream = (hipStream_t)hip_stream;
   c->mixed = p->precision == GRMHD_MIXED;
   (void)hipGetDevice(&c->device);
+  {
+    const hipError_t se = noalloc_scratch(c->device, &c->noalloc);
+    if (se != hipSuccess) {
+      delete c;
+      return fail(nullptr, GRMHD_EDEVICE, std::string("static scratch address: ") + hipGetErrorString(se));
+    }
+  }
   c->dx[0] = (p->x1max - p->x1min) / p->n1;
   c->dx[1] = (p->x2max - p->x2min) / p->n2;
   c->dx[2] = (p->x3max - p->x3min) / p->n3;
@@ -615,6 +622,23 @@ int grmhd_courant_dt(const grmhd_ctx* ctx, const double* ctop, int32_t nparts, d
       v[d] = std::fmax(v[d], c);
     }
   *dt = courant_dt(ctx->p.cfl, v, ctx->dx);
+  return GRMHD_OK;
+}
+
+int grmhd_divb_noalloc(grmhd_ctx* ctx, const double* P, double* max_divb) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (!P || !max_divb) return fail(ctx, GRMHD_EINVAL, "divb_noalloc: NULL argument");
+  const long long need = divb_blocks(ctx->d);
+  if (need > DIVB_NOALLOC_PARTS)
+    return fail(ctx, GRMHD_EINVAL,
+                "divb_noalloc: the grid needs " + std::to_string(need) + " partial maxima, the static scratch holds " +
+                    std::to_string(DIVB_NOALLOC_PARTS) + " (ceil(n1/64) ceil(n2/4) n3 must not exceed it)");
+  if (!ctx->noalloc) return fail(ctx, GRMHD_EDEVICE, "divb_noalloc: no static scratch on this device");
+  HIP_OR_FAIL(ctx, launch_divb_noalloc(ctx->p, ctx->d, ctx->t, P, ctx->noalloc, ctx->stream), "divb_noalloc");
+  HIP_OR_FAIL(ctx, hipMemcpyAsync(max_divb, ctx->noalloc + DIVB_NOALLOC_PARTS, sizeof(double), hipMemcpyDeviceToHost,
+                                  ctx->stream),
+              "copy");
+  HIP_OR_FAIL(ctx, hipStreamSynchronize(ctx->stream), "synchronize");
   return GRMHD_OK;
 }
 

@@ -9,11 +9,14 @@
 //   polar     - ghost row -1-m mirrors row m with u~2 and B2 negated;
 //   dirichlet - the ghosts keep the caller's values (copied from the base state
 //               into the half-step state).
+#include <mutex>
+
 #include "kernels.h"
 
 namespace {
 
 constexpr int GB = 64;           // threads per block of the x2 / x3 ghost fills
+constexpr int MAX_DEVICES = 64;  // devices the no-allocation scratch lookup keeps
 
 __device__ inline int wrap(int x, int n) {
   int r = x % n;
@@ -209,6 +212,39 @@ __global__ void divb_kernel(grmhd_problem p, Dims d, const double* __restrict__ 
   block_max_to(divb_at(p, d, cent, P, i, j, (int)blockIdx.z), out);
 }
 
+// The same blocks, each writing its maximum to its own slot of part[] (no
+// atomics, nothing to clear beforehand); then one block reduces the slots.
+__global__ __launch_bounds__(256) void divb_part_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
+                                                        const double* __restrict__ P, double* __restrict__ part) {
+  __shared__ double wmax[4];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int tid = threadIdx.x + blockDim.x * threadIdx.y;
+  const double v = wave_max(divb_at(p, d, cent, P, i, j, (int)blockIdx.z));
+  if ((tid & 63) == 0) wmax[tid >> 6] = v;
+  __syncthreads();
+  if (tid == 0) {
+    const int b = (int)(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z));
+    part[b] = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+  }
+}
+
+__global__ __launch_bounds__(256) void max_reduce_kernel(const double* __restrict__ part, int n,
+                                                         double* __restrict__ out) {
+  __shared__ double wmax[4];
+  double m = 0.0;
+  for (int q = (int)threadIdx.x; q < n; q += 256) m = fmax(m, part[q]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmax(fmax(wmax[0], wmax[1]), fmax(wmax[2], wmax[3]));
+}
+
+// Scratch of the no-allocation div B call: one double per block of
+// divb_part_kernel, and the result after them. One copy per device, held
+// until the process ends; the host reaches it only through the address
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) double scratch[DIVB_NOALLOC_PARTS + 32];
 
 __device__ void reset_counters(Counters* c, int mask) {
   if (mask & 1) c->ctop[0] = c->ctop[1] = c->ctop[2] = 0ull;
@@ -296,6 +332,37 @@ hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, c
                        Counters* ctr, hipStream_t s) {
   hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, s, ctr, 2);
   hipLaunchKernelGGL(divb_kernel, divb_grid(d), dim3(64, 4, 1), 0, s, p, d, t.cent, P, &ctr->divb);
+  return hipGetLastError();
+}
+
+long long divb_blocks(const Dims& d) {
+  const dim3 g = divb_grid(d);
+  return (long long)g.x * g.y * g.z;
+}
+
+// the address of scratch on each device, looked up once per device (with that
+// device current) and kept for the life of the process
+hipError_t noalloc_scratch(int device, double** ptr) {
+  static std::mutex mu;
+  static double* addr[MAX_DEVICES] = {};
+  *ptr = nullptr;
+  if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[device]) {
+    void* q = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[device] = (double*)q;
+  }
+  *ptr = addr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_divb_noalloc(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P,
+                               double* scr, hipStream_t s) {
+  const int n = (int)divb_blocks(d);
+  hipLaunchKernelGGL(divb_part_kernel, divb_grid(d), dim3(64, 4, 1), 0, s, p, d, t.cent, P, scr);
+  hipLaunchKernelGGL(max_reduce_kernel, dim3(1), dim3(256), 0, s, scr, n, scr + DIVB_NOALLOC_PARTS);
   return hipGetLastError();
 }
 

@@ -96,6 +96,7 @@ struct grmhd_ctx {
   void* F[3];
   int8_t* flags;
   Counters* ctr;
+  double* noalloc;  // this device's static scratch (grmhd_divb_noalloc), not owned
   UpdateParams up;
   double dx[3];
   std::string err;

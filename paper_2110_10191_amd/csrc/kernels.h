@@ -149,6 +149,15 @@ hipError_t launch_cons_to_prim(const Dims& d, const Tables& t, const UpdateParam
 hipError_t launch_divb(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P,
                        Counters* ctr, hipStream_t s);
 
+// div B without library-owned memory: per-block maxima in the device-resident
+// static scratch (DIVB_NOALLOC_PARTS slots, then the result at slot
+// DIVB_NOALLOC_PARTS). noalloc_scratch gives that array's address on the
+// device (which must be current); divb_blocks the number of slots a grid needs.
+constexpr int DIVB_NOALLOC_PARTS = 65536;
+long long divb_blocks(const Dims& d);
+hipError_t noalloc_scratch(int device, double** ptr);
+hipError_t launch_divb_noalloc(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P,
+                               double* scr, hipStream_t s);
 
 // electron heating: the ghost zones of the two entropies (the primitives'
 // rules without the axis sign change and the inflow fix); the advection of
