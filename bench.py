@@ -65,19 +65,14 @@ def split_design_bytes(kernel, prm, mixed):
     n1, n2, n3 = prm["n1"], prm["n2"], prm["n3"]
     fb = 4 if mixed else 8
     recon_reach = 3 if prm["recon"] == 1 else 2          # zones below / above+1 a face
-    if kernel in ("sweep1", "sweep2", "sweep3"):
-        d = int(kernel[-1])
-        n = [n1, n2, n3]
-        faces = 1
-        cells = 1
-        for e in range(3):
-            if e == d - 1:
-                faces *= n[e] + 1
-                cells *= n[e] + 2 * recon_reach
-            else:
-                faces *= n[e] + 2
-                cells *= n[e] + 2
-        geo = 22 * fb * (n1 + 2) * (n2 + 2)
+    if kernel == "sweeps":
+        # the state over the stencil's reach around the faces, once; the 7
+        # stored components of every face of the three directions; the three
+        # 2D face tables once
+        cells = (n1 + 2 * recon_reach) * (n2 + 2 * recon_reach) * (n3 + 2 * recon_reach)
+        faces = ((n1 + 1) * (n2 + 2) * (n3 + 2) + (n1 + 2) * (n2 + 1) * (n3 + 2)
+                 + (n1 + 2) * (n2 + 2) * (n3 + 1))
+        geo = 3 * 22 * fb * (n1 + 2) * (n2 + 2)
         return 64 * cells + 7 * fb * faces + geo
     if kernel == "update":
         zones = n1 * n2 * n3
@@ -386,7 +381,7 @@ def main():
     # roofline of the dominant kernel (the fused update: CT, source, U(P),
     # inversion, bounds; one launch per substep = Z/2 zone-cycles) with the
     # method's compulsory bytes per zone-cycle as the algorithmic bytes
-    dom = max(("sweep1", "sweep2", "sweep3", "update"), key=lambda k: kernels[k][0])
+    dom = max(("sweeps", "update"), key=lambda k: kernels[k][0])
     ms, n = kernels[dom]
     t_launch = ms / n / 1e3
     per_zc = compulsory_bytes_per_zone_cycle(prm)

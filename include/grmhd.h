@@ -275,17 +275,20 @@ GRMHD_API int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
  * electron calls (GRMHD_K_ELECTRONS: the scalar ghosts, advection and
  * heating) with HIP events on the context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
  * one kernel class, the summed device time in ms and the launch count since
- * the last clear; synchronises. Timing adds two event records per launch. */
+ * the last clear; synchronises. Timing adds two event records per launch.
+ * GRMHD_K_SWEEPS is the face-flux pass of all three directions, one launch per
+ * substep. */
 enum {
-  GRMHD_K_GHOSTS = 0, GRMHD_K_SWEEP1 = 1, GRMHD_K_SWEEP2 = 2, GRMHD_K_SWEEP3 = 3,
+  GRMHD_K_GHOSTS = 0, GRMHD_K_SWEEPS = 1, /* 2, 3: unused (no launches) */
   GRMHD_K_UPDATE = 4, GRMHD_K_FIXUP = 5, GRMHD_K_ELECTRONS = 6, GRMHD_K_COUNT = 7
 };
 GRMHD_API int grmhd_profile(grmhd_ctx *ctx, int32_t enable);
 GRMHD_API int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
-/* Thread-block tile of the sweep kernels (GRMHD_TILE_SWEEP) or of the update
- * and fixup kernels (GRMHD_TILE_UPDATE): tx zones along x1 by ty along x2, one
- * thread per zone or face; tx a power of two in [16, 256], tx * ty a multiple
+/* Thread-block tile of the face-flux kernel (GRMHD_TILE_SWEEP) or of the
+ * update and fixup kernels (GRMHD_TILE_UPDATE): tx zones along x1 by ty along
+ * x2, one thread per zone (the face-flux kernel computes up to the three
+ * lower faces of its zone); tx a power of two in [16, 256], tx * ty a multiple
  * of 64 and at most 512 (sweeps) or 256 (update). Defaults: sweeps 64 x 8,
  * update 64 x 4. Results do not depend on the tile. A batch uses the tiles of
  * its first job for every job. Errors: EINVAL. */

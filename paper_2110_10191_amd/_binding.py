@@ -19,7 +19,7 @@ EXPORTED = [
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step", "grmhd_batch_step_electrons",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
 ]
-KERNELS = {"ghosts": 0, "sweep1": 1, "sweep2": 2, "sweep3": 3, "update": 4, "fixup": 5, "electrons": 6}
+KERNELS = {"ghosts": 0, "sweeps": 1, "update": 4, "fixup": 5, "electrons": 6}
 NSCALAR = 2
 HEAT_MODELS = {"constant": 0, "kawazura": 1, "werner": 2, "rowan": 3, "howes": 4, "sharma": 5}
 TILES = {"sweep": 0, "update": 1}
@@ -289,7 +289,7 @@ def grmhd_profile(ctx, enable):
 
 
 def grmhd_profile_read(ctx, kernel):
-    """(total ms, launches) of one kernel class ('sweep1', 'update', ... or its id)."""
+    """(total ms, launches) of one kernel class ('sweeps', 'update', ... or its id)."""
     k = KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
     ms = ctypes.c_double()
     n = ctypes.c_int64()

@@ -146,11 +146,11 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
     HIP_OR_FAIL(c, launch_fill_scalar_ghosts(c->p, c->d, el->Es, el->Eb, s), "scalar ghost fill");
   }
   HIP_OR_FAIL(c, launch_reset(c->ctr, want_ctop ? (1 | 4) : 4, s), "reset");
-  for (int dir = 1; dir <= 3; ++dir) {
-    ProfScope ps(c->prof, s, GRMHD_K_SWEEP1 + dir - 1);
-    HIP_OR_FAIL(c, launch_sweep(dir, c->p.recon, c->mixed, c->d, c->t, c->p.gam, Ps, c->F[dir - 1],
-                                want_ctop ? c->ctr->ctop : nullptr, s),
-                "sweep");
+  {
+    ProfScope ps(c->prof, s, GRMHD_K_SWEEPS);
+    HIP_OR_FAIL(c, launch_sweeps(c->p.recon, c->mixed, c->d, c->t, c->p.gam, Ps, c->F, want_ctop ? c->ctr->ctop : nullptr,
+                                 s),
+                "sweeps");
   }
   if (el) {
     // before the update: in the corrector it overwrites the base state in place
@@ -516,10 +516,8 @@ int grmhd_get_dt(grmhd_ctx* ctx, double* P, double* dt) {
   hipStream_t s = ctx->stream;
   HIP_OR_FAIL(ctx, launch_fill_ghosts(ctx->p, ctx->d, ctx->t, P, P, s), "ghost fill");
   HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 1, s), "reset");
-  for (int dir = 1; dir <= 3; ++dir)
-    HIP_OR_FAIL(ctx, launch_sweep(dir, ctx->p.recon, ctx->mixed, ctx->d, ctx->t, ctx->p.gam, P, ctx->F[dir - 1],
-                                  ctx->ctr->ctop, s),
-                "sweep");
+  HIP_OR_FAIL(ctx, launch_sweeps(ctx->p.recon, ctx->mixed, ctx->d, ctx->t, ctx->p.gam, P, ctx->F, ctx->ctr->ctop, s),
+              "sweeps");
   return read_dt(ctx, dt);
 }
 

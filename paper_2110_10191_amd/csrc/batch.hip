@@ -84,9 +84,9 @@ hipError_t enqueue_step(grmhd_batch* b) {
       if ((e = launch_batch_electrons(bv, b->totals, b->mixed, b->recon, corr == 1, 1, s)) != hipSuccess) return e;
     }
     if ((e = launch_batch_reset(bv, corr ? (1 | 4) : 4, s)) != hipSuccess) return e;
-    for (int dir = 1; dir <= 3; ++dir) {
-      ProfScope ps(b->prof, s, GRMHD_K_SWEEP1 + dir - 1);
-      if ((e = launch_batch_sweeps(bv, b->totals, b->recon, b->mixed, corr == 1, corr == 1, dir, s)) != hipSuccess)
+    {
+      ProfScope ps(b->prof, s, GRMHD_K_SWEEPS);
+      if ((e = launch_batch_sweeps(bv, b->totals, b->recon, b->mixed, corr == 1, corr == 1, s)) != hipSuccess)
         return e;
     }
     if (b->electrons) {

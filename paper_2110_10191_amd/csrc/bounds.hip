@@ -405,8 +405,6 @@ void job_phase_blocks(const Dims& d, int counts[PH_COUNT]) {
   const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
   counts[PH_GHOST2] = tiles * 2 * NG * d.n3;
   counts[PH_GHOST3] = tiles * (d.n2 + 2 * NG) * 2 * NG;
-  counts[PH_SWEEP1] = (int)xcd_grid(d.n1 + 1, d.n2 + 2, d.n3 + 2, d.stx, d.sty);
-  counts[PH_SWEEP2] = (int)xcd_grid(d.n1 + 2, d.n2 + 1, d.n3 + 2, d.stx, d.sty);
-  counts[PH_SWEEP3] = (int)xcd_grid(d.n1 + 2, d.n2 + 2, d.n3 + 1, d.stx, d.sty);
+  counts[PH_SWEEP] = (int)sweep_blocks(d);
   counts[PH_UPDATE] = (int)xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
 }

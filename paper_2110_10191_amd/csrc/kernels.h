@@ -61,7 +61,7 @@ struct JobDesc {
   double fel;
 };
 
-enum { PH_GHOST1 = 0, PH_GHOST2, PH_GHOST3, PH_SWEEP1, PH_SWEEP2, PH_SWEEP3, PH_UPDATE, PH_COUNT };
+enum { PH_GHOST1 = 0, PH_GHOST2, PH_GHOST3, PH_SWEEP, PH_UPDATE, PH_COUNT };
 
 // offs[ph * (njobs + 1) + j] = first block of job j in phase ph; entry njobs = total
 struct BatchView {
@@ -99,9 +99,9 @@ void job_phase_blocks(const Dims& d, int counts[PH_COUNT]);
 // corrector = true: ghosts of P_h, fluxes of P_h, (P, P_h) -> P with dt.
 // totals[ph] = grid size of phase ph over the batch.
 hipError_t launch_batch_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s);
-// dir 1..3: one direction; 0: all three
+// the face fluxes of all three directions of every job
 hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon, bool mixed, bool corrector,
-                               bool want_ctop, int dir, hipStream_t s);
+                               bool want_ctop, hipStream_t s);
 // which: 1 the update, 2 the fixup, 3 both
 hipError_t launch_batch_update(const BatchView& bv, const int* totals, bool mixed, bool corrector, int which,
                                hipStream_t s);
@@ -120,10 +120,12 @@ hipError_t launch_geometry(const grmhd_problem& p, const Dims& d, const Tables& 
 hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,
                               const double* dirichlet_src, hipStream_t s);
 
-// face fluxes in direction dir (1..3) of state P; F is double (fp64) or float
-// (mixed). ctop may be null.
-hipError_t launch_sweep(int dir, int recon, bool mixed, const Dims& d, const Tables& t, double gam,
-                        const double* P, void* F, unsigned long long* ctop, hipStream_t s);
+// face fluxes of all three directions of state P into F[0..2] (double for
+// fp64, float for mixed); ctop (may be null) receives the per-direction
+// maximum signal speeds; sweep_blocks: the launch's grid size
+unsigned sweep_blocks(const Dims& d);
+hipError_t launch_sweeps(int recon, bool mixed, const Dims& d, const Tables& t, double gam, const double* P,
+                         void* const* F, unsigned long long* ctop, hipStream_t s);
 
 // the step is dt, or dt_scale * *dt_dev when dt_dev is not null
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up,

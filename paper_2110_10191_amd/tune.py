@@ -36,7 +36,7 @@ ROWS = (1, 2, 4, 8, 16)
 MAX_THREADS = {"sweep": 512, "update": 256}   # the kernels' launch bounds
 DEFAULT = {"sweep": (64, 8), "update": (64, 4)}
 
-SWEEP_CLASSES = ("sweep1", "sweep2", "sweep3")
+SWEEP_CLASSES = ("sweeps",)
 UPDATE_CLASSES = ("update", "fixup")
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "grmhd", "tiles.json")

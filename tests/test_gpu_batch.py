@@ -162,7 +162,7 @@ def test_profiled_batch_steps_equal_graph_replays(lib):
         dts, status = b.get()
         assert status == [0]
         if prof:
-            for name in ("ghosts", "sweep1", "sweep2", "sweep3", "update", "fixup"):
+            for name in ("ghosts", "sweeps", "update", "fixup"):
                 ms, n = b.profile_read(name)
                 assert n == 6 and ms > 0.0, name
             b.profile(False)

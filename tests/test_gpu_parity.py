@@ -374,37 +374,50 @@ def kicked_torus(n1=72, n2=40, n3=6, v=20.0, u_over_rho=1e-6, recon=problems.REC
     return prm, P0
 
 
-@pytest.mark.parametrize("v,u_over_rho,nsteps", [(20.0, 1e-6, 2), (100.0, 0.1, 3)], ids=["cold", "warm"])
-def test_torus_steps_with_fixups_fp64(lib, v, u_over_rho, nsteps):
+def conserved_error(P_gpu, P_orc, g):
+    """Relative L1 differences of the conserved variables U(P) of two states
+    (the oracle's prim_to_cons on both): mass and energy per component; the
+    three momenta, and the three field components, each normalised by the L1
+    norm of all three (a component that is physically near zero, B3 or the
+    torus's x2 momentum, would make its own norm ill-posed)."""
+    Ug = oracle.prim_to_cons(P_gpu, g)
+    Uo = oracle.prim_to_cons(P_orc, g)
+    d = np.abs(Ug - Uo).reshape(8, -1).sum(axis=1)
+    n = np.abs(Uo).reshape(8, -1).sum(axis=1)
+    return np.concatenate([d[:2] / n[:2], d[2:5] / n[2:5].sum(), d[5:] / n[5:].sum()])
+
+
+@pytest.mark.parametrize("v,u_over_rho", [(20.0, 1e-6), (100.0, 0.1)], ids=["cold", "warm"])
+def test_torus_step_with_fixups_fp64(lib, v, u_over_rho):
     """Step-level parity where inversions fail on a Kerr grid: the failure
-    count of every step and the state after the steps (fixup, then the bounds
-    on the repaired zones) against the oracle. Few steps: the zones next to a
-    cold relativistic stream recover u as a small difference of numbers ~Gamma^2
-    larger, which amplifies the rounding differences of two independent FP64
-    evaluations by that factor each step."""
+    count of the step (predictor and corrector) equals the oracle's, and the
+    state after it (fixup, then the bounds on the repaired zones) agrees in
+    its conserved variables to 1e-10. The comparison is made on U(P): next to
+    a relativistic stream that did not fail, the inversion recovers u as a
+    small difference of numbers Gamma^2 rho / u larger (1e8 for the cold
+    stream), so the primitive u of such zones is determined only to that
+    multiple of the rounding of U, and two independent FP64 evaluations differ
+    there by ~1e-8 relative however faithful both are; U itself is evolved
+    conservatively and stays well conditioned (its rounding grows by Gamma^2
+    at most)."""
     prm, P0 = kicked_torus(v=v, u_over_rho=u_over_rho)
     g = oracle.Grid(prm)
     dt = oracle.get_dt(P0, g)
-    P = P0
-    dts, fails = [], []
-    for _ in range(nsteps):
-        dts.append(dt)
-        P, dn, info = oracle.step(P, g, dt)
-        fails.append(info["fail_predictor"] + info["fail_corrector"])
-        dt = min(dn, 1.3 * dt)
-    assert sum(fails) > 0
+    P, _, info = oracle.step(P0, g, dt)
+    fails = info["fail_predictor"] + info["fail_corrector"]
+    assert fails > 0
     sim = lib.Sim(prm)
     Pd = sim.to_device(P0)
-    got_fails = []
-    for dt in dts:
-        sim.step(Pd, dt, want_dt_next=False)
-        got_fails.append(sim.step_failures())
+    sim.step(Pd, dt, want_dt_next=False)
+    got_fails = sim.step_failures()
     got = sim.to_host(Pd)
     sim.close()
-    err = rel_l1(interior(got, prm), interior(P, prm))
-    print("failed inversions per step: oracle", fails, "gpu", got_fails)
-    print("rel-L1", err)
+    err = conserved_error(got, P, g)
+    print("failed inversions: oracle", fails, "gpu", got_fails)
+    print("conserved rel-L1 (mass, energy, momenta / |all momenta|, field / |all field|)", err)
+    print("primitive rel-L1", rel_l1(interior(got, prm), interior(P, prm)))
     assert got_fails == fails
+    assert np.isfinite(got).all()
     assert (err <= 1e-10).all(), err
 
 
