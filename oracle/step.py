@@ -150,6 +150,8 @@ def face_fluxes(P, grid, d):
 
     Returns (F, ctop) on the padded index grid of ``P``; faces 0..n_d along d
     (padded NG..NG+n_d) are filled for every transverse index, the rest is NaN.
+    At an outflow boundary in x1 the rest-mass flux is clipped so that no mass
+    enters the domain.
 
     F = (F_L + F_R)/2 - ctop (U_R - U_L)/2,  ctop = max(c_max, c_min) with
     c_max = max(0, c+_L, c+_R), c_min = max(0, -c-_L, -c-_R).
@@ -176,6 +178,15 @@ def face_fluxes(P, grid, d):
     cmin = np.maximum(np.maximum(0.0, -cmL), -cmR)
     ctop = np.maximum(cmax, cmin)
     Fface = 0.5 * (FL + FR) - 0.5 * ctop * (UR - UL)
+    if d == 1:
+        # reading of the silent radial boundary: no mass enters through an
+        # outflow boundary, so the rest-mass flux through the inner radial face
+        # is at most 0 and through the outer one at least 0
+        bc = prm["bc"][0]
+        if bc[0] == BC_OUTFLOW:
+            Fface[0, ..., 0] = np.minimum(Fface[0, ..., 0], 0.0)
+        if bc[1] == BC_OUTFLOW:
+            Fface[0, ..., -1] = np.maximum(Fface[0, ..., -1], 0.0)
     F = np.full(P.shape, np.nan)
     C = np.full(P.shape[1:], np.nan)
     sl = [slice(None)] * 4

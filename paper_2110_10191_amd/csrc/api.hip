@@ -100,6 +100,8 @@ Dims make_dims(const grmhd_problem& p) {
   d.stx = d.utx = TILE_X;
   d.sty = SWEEP_TILE_Y;
   d.uty = TILE_Y;
+  d.out_lo = p.bc[0][0] == GRMHD_BC_OUTFLOW;
+  d.out_hi = p.bc[0][1] == GRMHD_BC_OUTFLOW;
   return d;
 }
 

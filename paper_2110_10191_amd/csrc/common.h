@@ -42,6 +42,7 @@ struct Dims {
   int ts;          // table component stride (= p2 * p1)
   int stx, sty;    // thread-block tile (x1 x x2) of the sweeps
   int utx, uty;    // thread-block tile of the update and fixup
+  int out_lo, out_hi;  // x1 lower / upper boundary is an outflow boundary
 };
 
 __host__ __device__ inline int cell_of(const Dims& d, int k, int j, int i) {

@@ -66,9 +66,16 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
   const T cmax = fmax(fmax(T(0), cpL), cpR);
   const T cmin = fmax(fmax(T(0), -cmL), -cmR);
   const T ct = fmax(cmax, cmin);
+  T fv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) fv[v] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * ct * (UR[v] - UL[v]);
+  // no mass enters through an outflow boundary: the rest-mass flux through
+  // the inner radial face is at most 0, through the outer one at least 0
+  if (D == 1 && d.out_lo && i == 0) fv[0] = fmin(fv[0], T(0));
+  if (D == 1 && d.out_hi && i == d.n1) fv[0] = fmax(fv[0], T(0));
 #pragma unroll
   for (int v = 0; v < NV; ++v)
-    if (v != 4 + D) F[v * d.sv + c] = T(0.5) * (FL[v] + FR[v]) - T(0.5) * ct * (UR[v] - UL[v]);
+    if (v != 4 + D) F[v * d.sv + c] = fv[v];
   bool inner;
   if (D == 1) inner = (j >= 0 && j < d.n2 && k >= 0 && k < d.n3);
   else if (D == 2) inner = (i >= 0 && i < d.n1 && k >= 0 && k < d.n3);

@@ -352,3 +352,33 @@ def test_step_with_a_failed_zone_at_the_seam_is_translation_invariant():
         b, _, _ = oracle.step(R, g, dt)
         bi = np.roll(interior(b, prm), -s, axis=1)
         assert np.allclose(bi, interior(a, prm), rtol=1e-12, atol=1e-14), s
+
+
+def test_no_mass_enters_through_the_radial_outflow_faces():
+    """The rest-mass flux through the inner radial face is never positive and
+    through the outer one never negative: against the same faces computed
+    without the outflow rule (Dirichlet x1 on the same filled state), the two
+    boundary faces are min(F, 0) and max(F, 0) and every other face and
+    component is unchanged. The grid starts at r = 3, outside the horizon,
+    and the state streams into the domain at both ends so that the clip acts
+    on both faces."""
+    import math
+    from oracle.step import face_fluxes
+    prm, P = problems.fm_torus(n1=24, n2=12, n3=2)
+    prm = dict(prm, x1min=math.log(3.0))
+    g = oracle.Grid(prm)
+    Q = P.copy()
+    Q[2, :, :, NG:NG + 2] = 3.0
+    Q[2, :, :, NG + 22:NG + 24] = -3.0
+    Q = fill_ghosts(Q, g)
+    F, _ = face_fluxes(Q, g, 1)
+    prm_d = dict(prm, bc=[[problems.BC_DIRICHLET, problems.BC_DIRICHLET], prm["bc"][1], prm["bc"][2]])
+    F0, _ = face_fluxes(Q, oracle.Grid(prm_d), 1)
+    K, J = slice(NG, NG + 2), slice(NG, NG + 12)
+    lo, hi = F0[0, K, J, NG], F0[0, K, J, NG + 24]
+    assert np.any(lo > 0.0) and np.any(hi < 0.0)            # the rule has something to do
+    assert np.array_equal(F[0, K, J, NG], np.minimum(lo, 0.0))
+    assert np.array_equal(F[0, K, J, NG + 24], np.maximum(hi, 0.0))
+    same = np.isfinite(F0)
+    same[0, :, :, NG] = same[0, :, :, NG + 24] = False
+    assert np.array_equal(F[same], F0[same])
