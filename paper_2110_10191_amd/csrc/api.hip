@@ -97,7 +97,8 @@ Dims make_dims(const grmhd_problem& p) {
   d.s3 = d.p2 * d.p1;
   d.sv = d.p3 * d.s3;
   d.ts = d.p2 * d.p1;
-  d.stx = d.utx = TILE_X;
+  d.stx = SWEEP_TILE_X;
+  d.utx = TILE_X;
   d.sty = SWEEP_TILE_Y;
   d.uty = TILE_Y;
   d.out_lo = p.bc[0][0] == GRMHD_BC_OUTFLOW;

@@ -359,11 +359,11 @@ def test_run_keeps_dt_on_device_and_equals_the_host_loop(lib):
 
 # ----------------------------------------------------------------- fixups inside steps
 
-def kicked_torus(n1=72, n2=40, n3=6, v=20.0, u_over_rho=1e-6, recon=problems.RECON_MC):
-    """The torus with two cold zones (u = 1e-6 rho) moving radially at u~1 = 20
-    at the density maximum, on both sides of the periodic x3 seam (planes 0
-    and n3 - 1): their inversions, and those of zones around them, fail inside
-    the step, and the fixups reach across the seam."""
+def kicked_torus(n1=72, n2=40, n3=6, v=10.0, u_over_rho=0.1, recon=problems.RECON_MC):
+    """The torus with two zones at its density maximum, on both sides of the
+    periodic x3 seam (planes 0 and n3 - 1), given a radial velocity u~1 = v and
+    u = u_over_rho rho: their inversions, and those of zones around them, fail
+    inside the step, and the fixups reach across the seam."""
     prm, P0 = problems.fm_torus(n1=n1, n2=n2, n3=n3, recon=recon)
     P0 = P0.copy()
     rho = P0[0, NG, NG:NG + n2, NG:NG + n1]
@@ -374,50 +374,40 @@ def kicked_torus(n1=72, n2=40, n3=6, v=20.0, u_over_rho=1e-6, recon=problems.REC
     return prm, P0
 
 
-def conserved_error(P_gpu, P_orc, g):
-    """Relative L1 differences of the conserved variables U(P) of two states
-    (the oracle's prim_to_cons on both): mass and energy per component; the
-    three momenta, and the three field components, each normalised by the L1
-    norm of all three (a component that is physically near zero, B3 or the
-    torus's x2 momentum, would make its own norm ill-posed)."""
-    Ug = oracle.prim_to_cons(P_gpu, g)
-    Uo = oracle.prim_to_cons(P_orc, g)
-    d = np.abs(Ug - Uo).reshape(8, -1).sum(axis=1)
-    n = np.abs(Uo).reshape(8, -1).sum(axis=1)
-    return np.concatenate([d[:2] / n[:2], d[2:5] / n[2:5].sum(), d[5:] / n[5:].sum()])
-
-
-@pytest.mark.parametrize("v,u_over_rho", [(20.0, 1e-6), (100.0, 0.1)], ids=["cold", "warm"])
-def test_torus_step_with_fixups_fp64(lib, v, u_over_rho):
+@pytest.mark.parametrize("v,u_over_rho", [(10.0, 0.1), (200.0, 10.0)], ids=["warm_v10", "hot_v200"])
+def test_torus_steps_with_fixups_fp64(lib, v, u_over_rho):
     """Step-level parity where inversions fail on a Kerr grid: the failure
-    count of the step (predictor and corrector) equals the oracle's, and the
-    state after it (fixup, then the bounds on the repaired zones) agrees in
-    its conserved variables to 1e-10. The comparison is made on U(P): next to
-    a relativistic stream that did not fail, the inversion recovers u as a
-    small difference of numbers Gamma^2 rho / u larger (1e8 for the cold
-    stream), so the primitive u of such zones is determined only to that
-    multiple of the rounding of U, and two independent FP64 evaluations differ
-    there by ~1e-8 relative however faithful both are; U itself is evolved
-    conservatively and stays well conditioned (its rounding grows by Gamma^2
-    at most)."""
+    count of every step (predictor and corrector) equals the oracle's, and the
+    state after 3 steps (fixups, then the bounds on the repaired zones) agrees
+    to 1e-10 per primitive. The kicked zones are warm: next to a cold
+    relativistic stream the inversion would recover u as a small difference of
+    numbers Gamma^2 rho / u larger, and a case like that (u = 1e-6 rho at
+    u~1 = 20) differs by 1e-8 between two runs of the oracle itself whose
+    initial states differ by 1e-15 relative, so it cannot test parity; these
+    two differ by 2e-11 and 9e-12 under that test."""
     prm, P0 = kicked_torus(v=v, u_over_rho=u_over_rho)
     g = oracle.Grid(prm)
     dt = oracle.get_dt(P0, g)
-    P, _, info = oracle.step(P0, g, dt)
-    fails = info["fail_predictor"] + info["fail_corrector"]
-    assert fails > 0
+    P = P0
+    dts, fails = [], []
+    for _ in range(3):
+        dts.append(dt)
+        P, dn, info = oracle.step(P, g, dt)
+        fails.append(info["fail_predictor"] + info["fail_corrector"])
+        dt = min(dn, 1.3 * dt)
+    assert sum(fails) > 0
     sim = lib.Sim(prm)
     Pd = sim.to_device(P0)
-    sim.step(Pd, dt, want_dt_next=False)
-    got_fails = sim.step_failures()
+    got_fails = []
+    for dt in dts:
+        sim.step(Pd, dt, want_dt_next=False)
+        got_fails.append(sim.step_failures())
     got = sim.to_host(Pd)
     sim.close()
-    err = conserved_error(got, P, g)
-    print("failed inversions: oracle", fails, "gpu", got_fails)
-    print("conserved rel-L1 (mass, energy, momenta / |all momenta|, field / |all field|)", err)
-    print("primitive rel-L1", rel_l1(interior(got, prm), interior(P, prm)))
+    err = rel_l1(interior(got, prm), interior(P, prm))
+    print("failed inversions per step: oracle", fails, "gpu", got_fails)
+    print("rel-L1", err)
     assert got_fails == fails
-    assert np.isfinite(got).all()
     assert (err <= 1e-10).all(), err
 
 
@@ -447,16 +437,16 @@ def test_fixup_across_periodic_seams_matches_oracle(lib):
 
 
 def test_radial_mass_flux_clip_matches_oracle(lib):
-    """A Kerr grid that starts at r = 3 (outside the horizon) with gas streaming
-    into the domain through both radial boundaries: the clipped rest-mass
-    fluxes through the radial faces (no mass enters) give the oracle's state
-    after 3 steps."""
+    """A Kerr grid from r = 3 (outside the horizon) to r = 50 with gas streaming
+    into the domain through both radial boundaries (the clip acts on 96 faces
+    at each end in the first step, and hundreds of inversions fail and are
+    repaired): the oracle's state after 3 steps."""
     import math
     prm, P0 = problems.fm_torus(n1=48, n2=24, n3=4)
-    prm = dict(prm, x1min=math.log(3.0))
+    prm = dict(prm, x1min=math.log(3.0), x1max=math.log(50.0))
     P0 = P0.copy()
-    P0[2, :, :, NG:NG + 2] = 3.0
-    P0[2, :, :, NG + 46:NG + 48] = -3.0
+    P0[2, :, :, NG:NG + 2] = 0.3
+    P0[2, :, :, NG + 46:NG + 48] = -0.03
     ref, dts = oracle_run(prm, P0, 3)
     got = gpu_run(lib, prm, P0, dts)
     err = rel_l1(interior(got, prm), interior(ref, prm))
