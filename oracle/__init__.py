@@ -15,7 +15,10 @@ named in the docstring of the function that takes it.
 
 Layout: primitives are float64 arrays ``[8, n3+6, n2+6, n1+6]`` (three ghost
 layers per side, x1 fastest) in the order rho, u, u~1, u~2, u~3, B1, B2, B3.
-Geometry is axisymmetric: 2D tables ``[..., n2+6, n1+6]`` broadcast over x3.
+Geometry of the axisymmetric coordinates (Minkowski, MKS, FMKS) is 2D tables
+``[..., n2+6, n1+6]`` broadcast over x3; Cartesian Kerr-Schild, whose metric
+depends on all three code coordinates, has 3D tables ``[..., n3+6, n2+6, n1+6]``
+(``Grid.k3``), with its own x3-face table.
 
 Electron heating (``oracle.electrons``): two advected entropies per zone and
 the partition of the dissipated heat by a heating model; readings E1-E6 are

@@ -61,7 +61,7 @@ import numpy as np
 from .grid import NG
 from .physics import fluid_state
 from .recon import reconstruct
-from .step import (_interior, _geo2, fill_ghosts, substep, dt_from_ctop, AXIS, BC_PERIODIC, BC_OUTFLOW,
+from .step import (_interior, fill_ghosts, substep, dt_from_ctop, AXIS, BC_PERIODIC, BC_OUTFLOW,
                    BC_POLAR, BC_DIRICHLET)
 
 GAM_E = 4.0 / 3.0
@@ -184,7 +184,7 @@ def electron_substep(Es, Eb, Pb, Pn, mass, grid, dt, model, fel):
     dx1, dx2, dx3 = grid.dx
     div = ((F1[:, K, J, Ip] - F1[:, K, J, I]) / dx1 + (F2[:, K, Jp, I] - F2[:, K, J, I]) / dx2
            + (F3[:, Kp, J, I] - F3[:, K, J, I]) / dx3)
-    geo = _geo2(grid.cent, J, I)
+    geo = grid.sub(grid.cent, K, J, I)
     gdet = geo["gdet"]
     sb = fluid_state(Pb, geo, gam)
     Ub = gdet * Pb[0] * sb["ucon"][0] * Eb

@@ -34,12 +34,6 @@ def _interior(n3, n2, n1):
     return (slice(None), slice(NG, NG + n3), slice(NG, NG + n2), slice(NG, NG + n1))
 
 
-def _geo2(geo, js=slice(None), is_=slice(None)):
-    """Slice every 2D table of a geometry dict in (j, i)."""
-    out = {}
-    for k, v in geo.items():
-        out[k] = v[..., js, is_]
-    return out
 
 
 # ----------------------------------------------------------------------------- boundaries
@@ -102,7 +96,7 @@ def fill_ghosts(P, grid, do_x3=True):
         if t == BC_OUTFLOW:
             gs = slice(0, NG) if side == 0 else slice(NG + n1, NG + n1 + NG)
             sub = P[:, K, J, gs]
-            _inflow_fix(sub, _geo2(grid.cent, J, gs), side)
+            _inflow_fix(sub, grid.sub(grid.cent, K, J, gs), side)
             P[:, K, J, gs] = sub
     # x2
     for side in (0, 1):
@@ -162,11 +156,9 @@ def face_fluxes(P, grid, d):
     n = P.shape[ax] - 2 * NG
     f0, f1 = NG, NG + n + 1
     PL, PR = reconstruct(P, ax, prm["recon"], f0, f1)
-    geo = grid.face[d]
-    if d == 1:
-        geo = _geo2(geo, slice(None), slice(f0, f1))
-    elif d == 2:
-        geo = _geo2(geo, slice(f0, f1), slice(None))
+    sl = [slice(None)] * 3                 # (k, j, i) of the face table
+    sl[ax - 1] = slice(f0, f1)
+    geo = grid.sub(grid.face[d], *sl)
     gdet = geo["gdet"]
     sL = fluid_state(PL, geo, gam)
     sR = fluid_state(PR, geo, gam)
@@ -360,6 +352,8 @@ def substep(Ps, Pb, grid, dt, mass_flux=False, window=False):
     gam = prm["gam"]
     nk = Ps.shape[1] - 2 * NG
     n1, n2 = grid.n[0], grid.n[1]
+    if grid.k3 and nk != grid.n[2]:
+        raise ValueError("3D geometry tables need the whole x3 extent")
     F1, C1 = face_fluxes(Ps, grid, 1)
     F2, C2 = face_fluxes(Ps, grid, 2)
     F3, C3 = face_fluxes(Ps, grid, 3)
@@ -369,8 +363,9 @@ def substep(Ps, Pb, grid, dt, mass_flux=False, window=False):
     dx1, dx2, dx3 = grid.dx
     div = ((F1[:, K, J, Ip] - F1[:, K, J, I]) / dx1 + (F2[:, K, Jp, I] - F2[:, K, J, I]) / dx2
            + (F3[:, Kp, J, I] - F3[:, K, J, I]) / dx3)
-    geo = _geo2(grid.cent, J, I)
-    conn = grid.conn[..., J, I]
+    geo = grid.sub(grid.cent, K, J, I)
+    conn = grid.sub(grid.conn, K, J, I)
+    r = grid.sub(grid.r, K, J, I) if grid.kerr else None
     Psi = Ps[:, K, J, I]
     S = source(Psi, geo, conn, gam)
     U0 = conserved(fluid_state(Pb, geo, gam), geo["gdet"])
@@ -379,11 +374,11 @@ def substep(Ps, Pb, grid, dt, mass_flux=False, window=False):
     Ustar = U0 + dt * rhs
     Pn, failed = invert(Ustar, Psi, geo, gam)
     if prm["floors"]:
-        floors(Pn, geo, grid.r[J, I], prm)
+        floors(Pn, geo, r, prm)
     if failed.any():
         fixup(Pn, failed, periodic_axes(prm, window))
         if prm["floors"]:
-            floors(Pn, geo, grid.r[J, I], prm, mask=failed)
+            floors(Pn, geo, r, prm, mask=failed)
     cmax = (np.nanmax(C1[K, J, NG:NG + n1 + 1]), np.nanmax(C2[K, NG:NG + n2 + 1, I]),
             np.nanmax(C3[NG:NG + nk + 1, J, I]))
     if mass_flux:
@@ -469,22 +464,23 @@ def prim_to_cons(P, grid):
     """U on the interior zones of a padded primitive array."""
     n1, n2, n3 = grid.n
     it = _interior(n3, n2, n1)
-    geo = _geo2(grid.cent, slice(NG, NG + n2), slice(NG, NG + n1))
+    geo = grid.sub(grid.cent, *it[1:])
     return conserved(fluid_state(P[it], geo, grid.prm["gam"]), geo["gdet"])
 
 
 def cons_to_prim(U, guess, grid, do_floors=True, do_fixup=True):
     """Invert interior conserved variables (then bounds and fixup)."""
     n1, n2, n3 = grid.n
-    J, I = slice(NG, NG + n2), slice(NG, NG + n1)
-    geo = _geo2(grid.cent, J, I)
+    K, J, I = slice(NG, NG + n3), slice(NG, NG + n2), slice(NG, NG + n1)
+    geo = grid.sub(grid.cent, K, J, I)
+    r = grid.sub(grid.r, K, J, I) if grid.kerr else None
     P, failed = invert(U, guess, geo, grid.prm["gam"])
     if do_floors and grid.prm["floors"]:
-        floors(P, geo, grid.r[J, I], grid.prm)
+        floors(P, geo, r, grid.prm)
     if do_fixup and failed.any():
         fixup(P, failed, periodic_axes(grid.prm))
         if do_floors and grid.prm["floors"]:
-            floors(P, geo, grid.r[J, I], grid.prm, mask=failed)
+            floors(P, geo, r, grid.prm, mask=failed)
     return P, failed
 
 
@@ -500,7 +496,7 @@ def divb(P, grid):
     prm = grid.prm
     n1, n2, n3 = grid.n
     it = _interior(n3, n2, n1)
-    gd = grid.cent["gdet"][NG:NG + n2, NG:NG + n1]
+    gd = grid.sub(grid.cent["gdet"], *it[1:])
     G = [P[it][B1 + d] * gd for d in range(3)]
     per = [prm["bc"][d][0] == BC_PERIODIC for d in range(3)]
 

@@ -4,7 +4,7 @@ import math
 
 NG = 3                      # ghost layers on each side of every direction
 
-MINKOWSKI_CART, KERR_MKS, KERR_FMKS = 0, 1, 2
+MINKOWSKI_CART, KERR_MKS, KERR_FMKS, KERR_CKS = 0, 1, 2, 3
 RECON_MC, RECON_WENO5 = 0, 1
 FP64, MIXED = 0, 1
 BC_PERIODIC, BC_OUTFLOW, BC_POLAR, BC_DIRICHLET = 0, 1, 2, 3
