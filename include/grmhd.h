@@ -58,7 +58,7 @@ typedef enum {
   GRMHD_ESTATE = -5        /* a non-finite value appeared in the evolved state */
 } grmhd_status;
 
-enum { GRMHD_MINKOWSKI_CART = 0, GRMHD_KERR_MKS = 1, GRMHD_KERR_FMKS = 2 };
+enum { GRMHD_MINKOWSKI_CART = 0, GRMHD_KERR_MKS = 1, GRMHD_KERR_FMKS = 2, GRMHD_KERR_CKS = 3 };
 enum { GRMHD_RECON_MC = 0, GRMHD_RECON_WENO5 = 1 };
 enum { GRMHD_FP64 = 0, GRMHD_MIXED = 1 };
 enum { GRMHD_BC_PERIODIC = 0, GRMHD_BC_OUTFLOW = 1, GRMHD_BC_POLAR = 2, GRMHD_BC_DIRICHLET = 3 };
@@ -78,10 +78,22 @@ enum { GRMHD_OPT_FLOORS = 1, GRMHD_OPT_FIXUP = 2 };
  *   KERR_FMKS: as MKS, with theta blended towards the polynomial
  *              theta_J = N y (1 + (y/poly_xt)^poly_alpha/(poly_alpha+1)) + pi/2,
  *              y = 2 x2 - 1, by exp(-mks_smooth (x1 - x1min)).
+ *   KERR_CKS:  Cartesian Kerr-Schild, (x1, x2, x3) = (x, y, z), metric
+ *              eta + f l l with f = 2 r^3/(r^4 + a^2 z^2), l = (1, (r x + a y)/(r^2 + a^2),
+ *              (r y - a x)/(r^2 + a^2), z/r) and r the positive root of
+ *              r^4 - (x^2 + y^2 + z^2 - a^2) r^2 - a^2 z^2 = 0 (Implementation Notes:
+ *              a change of coordinates or background spacetime). The metric
+ *              depends on all three coordinates: the geometry tables are 3D
+ *              (about 1.4 KB of device memory per zone, counted by
+ *              grmhd_context_bytes; at most 2^25 zones, ghosts and x1
+ *              padding included). Boundaries PERIODIC or DIRICHLET only; the
+ *              box, ghosts included, must lie outside the unit sphere
+ *              x^2 + y^2 + z^2 < 1 (so r > 0 and the metric is regular).
  * Zone centres sit at x_d = xdmin + (i + 1/2) (xdmax - xdmin)/nd.
  * bc[d][side]: boundary type of direction d (0 = x1) at its lower (0) / upper (1)
- * edge; PERIODIC on both sides or neither; OUTFLOW only in x1; POLAR only in
- * x2; DIRICHLET keeps the ghost values the caller stored in the state.
+ * edge; PERIODIC on both sides or neither; OUTFLOW only in x1 of MKS / FMKS;
+ * POLAR only in x2 of MKS / FMKS; DIRICHLET keeps the ghost values the caller
+ * stored in the state.
  * floors: 1 applies the bounds (needs a Kerr metric: they use r). */
 typedef struct grmhd_problem {
   int32_t n1, n2, n3;

@@ -38,7 +38,7 @@ int hip_fail(grmhd_ctx* c, hipError_t e, const char* where) {
 int validate(const grmhd_problem* p, std::string& why) {
   if (!p) { why = "problem is NULL"; return GRMHD_EINVAL; }
   if (p->n1 < 1 || p->n2 < 1 || p->n3 < 1) { why = "n1, n2, n3 must be >= 1"; return GRMHD_EINVAL; }
-  if (p->coords < GRMHD_MINKOWSKI_CART || p->coords > GRMHD_KERR_FMKS) { why = "unknown coords"; return GRMHD_EINVAL; }
+  if (p->coords < GRMHD_MINKOWSKI_CART || p->coords > GRMHD_KERR_CKS) { why = "unknown coords"; return GRMHD_EINVAL; }
   if (p->recon != GRMHD_RECON_MC && p->recon != GRMHD_RECON_WENO5) { why = "unknown recon"; return GRMHD_EINVAL; }
   if (p->precision != GRMHD_FP64 && p->precision != GRMHD_MIXED) { why = "unknown precision"; return GRMHD_EINVAL; }
   if (!(p->gam > 1.0) || !(p->cfl > 0.0) || !std::isfinite(p->gam) || !std::isfinite(p->cfl)) {
@@ -75,6 +75,23 @@ int validate(const grmhd_problem* p, std::string& why) {
     if (!(std::fabs(p->a) < 1.0)) { why = "need |a| < 1"; return GRMHD_EINVAL; }
     if (p->coords == GRMHD_KERR_FMKS && !(p->poly_xt > 0.0)) { why = "need poly_xt > 0"; return GRMHD_EINVAL; }
   }
+  if (p->coords == GRMHD_KERR_CKS) {
+    for (int d = 0; d < 3; ++d)
+      for (int s = 0; s < 2; ++s)
+        if (p->bc[d][s] != GRMHD_BC_PERIODIC && p->bc[d][s] != GRMHD_BC_DIRICHLET) {
+          why = "Cartesian Kerr-Schild boundaries are periodic or Dirichlet";
+          return GRMHD_EINVAL;
+        }
+    // the point of the padded box nearest the origin must have R >= 1 (then r > 0)
+    double r2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double pad = NG * (hi[d] - lo[d]) / n[d];
+      const double a = lo[d] - pad, b = hi[d] + pad;
+      const double q = a > 0.0 ? a : (b < 0.0 ? -b : 0.0);
+      r2 += q * q;
+    }
+    if (!(r2 >= 1.0)) { why = "the Cartesian Kerr-Schild box (ghosts included) must lie outside the unit sphere"; return GRMHD_EINVAL; }
+  }
   if (p->floors && !(p->sigma_max > 0 && p->uorho_max > 0 && p->gamma_max > 1.0 && p->beta_min >= 0)) {
     why = "bad floor parameters";
     return GRMHD_EINVAL;
@@ -82,6 +99,10 @@ int validate(const grmhd_problem* p, std::string& why) {
   const long long p1 = ((p->n1 + 2 * NG + 7) / 8) * 8;
   const long long cells = p1 * (p->n2 + 2 * NG) * (long long)(p->n3 + 2 * NG);
   if (cells * NV >= (1ll << 31)) { why = "grid too large for 32-bit indexing of one state"; return GRMHD_EINVAL; }
+  if (p->coords == GRMHD_KERR_CKS && cells * N_CENT >= (1ll << 31)) {
+    why = "grid too large for 32-bit indexing of the 3D geometry tables (at most 2^25 padded zones)";
+    return GRMHD_EINVAL;
+  }
   return GRMHD_OK;
 }
 
@@ -96,7 +117,9 @@ Dims make_dims(const grmhd_problem& p) {
   d.s2 = d.p1;
   d.s3 = d.p2 * d.p1;
   d.sv = d.p3 * d.s3;
-  d.ts = d.p2 * d.p1;
+  const bool k3 = p.coords == GRMHD_KERR_CKS;
+  d.ts = k3 ? d.sv : d.p2 * d.p1;
+  d.tk = k3 ? d.s3 : 0;
   d.stx = SWEEP_TILE_X;
   d.utx = TILE_X;
   d.sty = SWEEP_TILE_Y;
@@ -107,7 +130,10 @@ Dims make_dims(const grmhd_problem& p) {
 }
 
 void free_all(grmhd_ctx* c) {
-  void* ptrs[] = {c->t.cent, c->t.f1, c->t.f2, c->t.centf, c->t.f1f, c->t.f2f,
+  // 2D tables alias the x3-face tables to the centre ones
+  void* f3 = c->t.f3 != c->t.cent ? (void*)c->t.f3 : nullptr;
+  void* f3f = c->t.f3f != c->t.centf ? (void*)c->t.f3f : nullptr;
+  void* ptrs[] = {c->t.cent, c->t.f1, c->t.f2, f3, c->t.centf, c->t.f1f, c->t.f2f, f3f,
                   c->Ph, c->F[0], c->F[1], c->F[2], c->flags, c->ctr, c->Eh, c->Uk};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -320,7 +346,8 @@ int grmhd_context_bytes(const grmhd_problem* p, int64_t* ctx_bytes, int64_t* sta
   const Dims d = make_dims(*p);
   const size_t ts = (size_t)d.ts, sv = (size_t)d.sv;
   const size_t fsz = p->precision == GRMHD_MIXED ? sizeof(float) : sizeof(double);
-  const size_t tables = (N_CENT + 2 * N_FACE) * ts * sizeof(double) + 3 * N_FACE * ts * sizeof(float);
+  const int nface = d.tk ? 3 : 2;  // x3-face tables of their own (3D tables only)
+  const size_t tables = (N_CENT + nface * N_FACE) * ts * sizeof(double) + (1 + nface) * N_FACE * ts * sizeof(float);
   const size_t scratch = NV * sv * sizeof(double) + 3 * NV * sv * fsz + sv + sizeof(Counters);
   *ctx_bytes = (int64_t)(tables + scratch);
   *state_bytes = (int64_t)(NV * sv * sizeof(double));
@@ -380,6 +407,8 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
             dalloc(&c->t.centf, N_FACE * ts * sizeof(float)) == hipSuccess &&
             dalloc(&c->t.f1f, N_FACE * ts * sizeof(float)) == hipSuccess &&
             dalloc(&c->t.f2f, N_FACE * ts * sizeof(float)) == hipSuccess &&
+            (!c->d.tk || (dalloc(&c->t.f3, N_FACE * ts * sizeof(double)) == hipSuccess &&
+                          dalloc(&c->t.f3f, N_FACE * ts * sizeof(float)) == hipSuccess)) &&
             dalloc(&c->Ph, NV * sv * sizeof(double)) == hipSuccess &&
             dalloc(&c->F[0], NV * sv * fsz) == hipSuccess && dalloc(&c->F[1], NV * sv * fsz) == hipSuccess &&
             dalloc(&c->F[2], NV * sv * fsz) == hipSuccess && dalloc(&c->flags, sv) == hipSuccess &&
@@ -389,6 +418,10 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
     free_all(c);
     delete c;
     return fail(nullptr, GRMHD_ENOMEM, "device allocation failed");
+  }
+  if (!c->d.tk) {
+    c->t.f3 = c->t.cent;
+    c->t.f3f = c->t.centf;
   }
   // one-time clears (outside any captured work); padding stays finite
   hipError_t e = hipMemsetAsync(c->t.cent, 0, N_CENT * ts * sizeof(double), c->stream);

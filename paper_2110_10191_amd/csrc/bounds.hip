@@ -68,7 +68,7 @@ __device__ void ghost_x1_body(const grmhd_problem& p, const Dims& d, const doubl
   const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n1) : (side == 0 ? 0 : d.n1 - 1);
   const int cs = cell_of(d, k, j, src);
   for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
-  if (!SCALAR && type == GRMHD_BC_OUTFLOW) inflow_fix(P, d.sv, cg, cent, d.ts, tab_of(d, j, g), side);
+  if (!SCALAR && type == GRMHD_BC_OUTFLOW) inflow_fix(P, d.sv, cg, tab_plane(cent, d, k), d.ts, tab_of(d, j, g), side);
 }
 
 __device__ inline int ghost_tiles(const Dims& d) { return (d.n1 + 2 * NG + GB - 1) / GB; }
@@ -188,7 +188,7 @@ __device__ double divb_at(const grmhd_problem& p, const Dims& d, const double* _
   const int im = wrap(i - 1, d.n1), jm = wrap(j - 1, d.n2), km = wrap(k - 1, d.n3);
   // G_d(kk, jj, ii) = sqrt(-g) B^d
   auto G = [&](int v, int kk, int jj, int ii) {
-    return cent[T_GDET * d.ts + tab_of(d, jj, ii)] * P[(5 + v) * d.sv + cell_of(d, kk, jj, ii)];
+    return tab_plane(cent, d, kk)[T_GDET * d.ts + tab_of(d, jj, ii)] * P[(5 + v) * d.sv + cell_of(d, kk, jj, ii)];
   };
   // sum over the two transverse offsets, differencing along the direction
   const double s1 = (G(0, k, j, i) - G(0, k, j, im)) + (G(0, k, jm, i) - G(0, k, jm, im)) +

@@ -2,10 +2,13 @@
 //
 // Layout (see grmhd.h): a state is [8][n3+6][n2+6][n1p] float64, x1 fastest.
 // Face fluxes use the same layout: F_d at cell (k, j, i) is the flux through
-// the lower d-face of that cell. Geometry is axisymmetric and stored as 2D
-// tables [component][n2+6][n1p]: centre tables (metric, inverse, sqrt(-g),
-// lapse, connection, floor scales) and x1-/x2-face tables (metric, inverse,
-// sqrt(-g), lapse). x3 faces share the centre geometry.
+// the lower d-face of that cell. Geometry tables hold centre quantities
+// (metric, inverse, sqrt(-g), lapse, connection, floor scales) and face
+// quantities (metric, inverse, sqrt(-g), lapse) per direction. Axisymmetric
+// coordinates store them as 2D tables [component][n2+6][n1p] (k stride 0),
+// and the x3 faces share the centre geometry; Cartesian Kerr-Schild, whose
+// metric depends on x3, stores 3D tables [component][n3+6][n2+6][n1p] (k
+// stride = the state's) with an x3-face table of its own.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,7 +42,8 @@ struct Dims {
   int s2;          // j stride (= p1)
   int s3;          // k stride (= p2 * p1)
   int sv;          // variable stride (= p3 * p2 * p1)
-  int ts;          // table component stride (= p2 * p1)
+  int ts;          // table component stride (p2 * p1, or p3 * p2 * p1 for 3D tables)
+  int tk;          // table k stride (0 for 2D tables, s3 for 3D)
   int stx, sty;    // thread-block tile (x1 x x2) of the sweeps
   int utx, uty;    // thread-block tile of the update and fixup
   int out_lo, out_hi;  // x1 lower / upper boundary is an outflow boundary
@@ -48,7 +52,13 @@ struct Dims {
 __host__ __device__ inline int cell_of(const Dims& d, int k, int j, int i) {
   return (k + NG) * d.s3 + (j + NG) * d.s2 + (i + NG);
 }
+// point index of (j, i) within one x3 plane of the tables; tab_plane gives the
+// plane of x3 index k (the only plane of 2D tables)
 __host__ __device__ inline int tab_of(const Dims& d, int j, int i) { return (j + NG) * d.s2 + (i + NG); }
+template <typename S>
+__host__ __device__ inline const S* tab_plane(const S* tab, const Dims& d, int k) {
+  return tab + (size_t)(k + NG) * (size_t)d.tk;
+}
 
 // Loads as (wave-uniform base pointer) + (32-bit unsigned byte offset):
 // the backend can then keep the base in scalar registers and share one 32-bit
@@ -66,7 +76,7 @@ struct Geo {
   T alpha;
 };
 
-// component c of a table lives at tab + c * ts; off is the 2D point index
+// component c of a table lives at tab + c * ts; off is the point index (tab_of)
 template <typename T, typename S>
 __device__ inline void load_geo(Geo<T>& g, const S* __restrict__ tab, int ts, int off) {
   const unsigned bo = (unsigned)off * (unsigned)sizeof(S);

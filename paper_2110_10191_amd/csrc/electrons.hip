@@ -92,10 +92,11 @@ __device__ void scalar_advect_body(const Dims& d, const double* __restrict__ cen
 
   // rest-mass density of the base state: sqrt(-g) rho u^t, u^t = Gamma / alpha
   const int toff = tab_of(d, j, i);
+  const double* ck = tab_plane(cent, d, tk.k);
   double gcov[10];
 #pragma unroll
-  for (int m = 0; m < 10; ++m) gcov[m] = cent[(T_GCOV + m) * d.ts + toff];
-  const double gdet = cent[T_GDET * d.ts + toff], alpha = cent[T_ALPHA * d.ts + toff];
+  for (int m = 0; m < 10; ++m) gcov[m] = ck[(T_GCOV + m) * d.ts + toff];
+  const double gdet = ck[T_GDET * d.ts + toff], alpha = ck[T_ALPHA * d.ts + toff];
   const double ut = sqrt(lorentz_sq(gcov, Pb[2 * d.sv + c], Pb[3 * d.sv + c], Pb[4 * d.sv + c])) / alpha;
   const double D = gdet * Pb[c] * ut;
 #pragma unroll
@@ -181,7 +182,7 @@ __device__ void electron_heat_body(const Dims& d, const double* __restrict__ cen
     P[d.sv + c] = umax;
   }
   Geo<double> g;
-  load_geo(g, cent, d.ts, tab_of(d, j, i));
+  load_geo(g, tab_plane(cent, d, tk.k), d.ts, tab_of(d, j, i));
   Fluid<double> f;
   fluid_state(p, g, gam, f);
   const double D = g.gdet * rho * f.ucon[0];

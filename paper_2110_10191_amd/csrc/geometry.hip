@@ -1,10 +1,18 @@
-// Geometry tables: metric, inverse, sqrt(-g) and lapse at zone centres and x1/x2
+// Geometry tables: metric, inverse, sqrt(-g) and lapse at zone centres and
 // faces; connection at centres by centred differences of the metric; floor
 // scales. Implementation Notes section: every metric-dependent quantity is
-// evaluated numerically from an analytic line element, and the coordinates act
-// as static mesh refinement (MKS / funky MKS concentrate zones towards the
-// disk midplane).
+// evaluated numerically from an analytic line element, the coordinates act as
+// static mesh refinement (MKS / funky MKS concentrate zones towards the disk
+// midplane), and another coordinate system or stationary spacetime is a small
+// change: Cartesian Kerr-Schild (metric eta + f l l in (t, x, y, z)) makes
+// every table depend on x3, so its tables are 3D with an x3-face table.
 #include "kernels.h"
+
+// No fused multiply-adds here: the connection's centred differences (step
+// 1e-5) turn a one-ulp change of the metric into a 1e-10 change of Gamma, so
+// every table value is the plain sequence of correctly rounded operations its
+// formula spells out.
+#pragma clang fp contract(off)
 
 namespace {
 
@@ -42,8 +50,31 @@ __device__ void theta_derivs(double x1, double x2, const grmhd_problem& p, doubl
   d2 = dtg + e * (dtj - dtg);
 }
 
+// radius of a Cartesian Kerr-Schild point: the positive root r of
+// r^4 - (R^2 - a^2) r^2 - a^2 z^2 = 0, R^2 = x^2 + y^2 + z^2
+__device__ double cks_r(double x, double y, double z, double a) {
+  const double h = 0.5 * (x * x + y * y + z * z - a * a);
+  return sqrt(h + sqrt(h * h + a * a * z * z));
+}
+
+// Cartesian Kerr-Schild: g = eta + f l l with f = 2 r^3 / (r^4 + a^2 z^2) and
+// the null covector l = (1, (r x + a y)/(r^2 + a^2), (r y - a x)/(r^2 + a^2), z/r)
+__device__ void gcov_cks(double x, double y, double z, double a, double g[4][4]) {
+  const double r = cks_r(x, y, z, a);
+  const double r2 = r * r;
+  const double f = 2.0 * r2 * r / (r2 * r2 + a * a * z * z);
+  const double ra = r2 + a * a;
+  const double l[4] = {1.0, (r * x + a * y) / ra, (r * y - a * x) / ra, z / r};
+  for (int m = 0; m < 4; ++m)
+    for (int n = 0; n < 4; ++n) g[m][n] = f * l[m] * l[n] + (m != n ? 0.0 : (m == 0 ? -1.0 : 1.0));
+}
+
 // covariant metric in code coordinates, full 4x4
-__device__ void gcov_code(double x1, double x2, const grmhd_problem& p, double g[4][4]) {
+__device__ void gcov_code(double x1, double x2, double x3, const grmhd_problem& p, double g[4][4]) {
+  if (p.coords == GRMHD_KERR_CKS) {
+    gcov_cks(x1, x2, x3, p.a, g);
+    return;
+  }
   for (int m = 0; m < 4; ++m)
     for (int n = 0; n < 4; ++n) g[m][n] = 0.0;
   if (p.coords == GRMHD_MINKOWSKI_CART) {
@@ -112,10 +143,10 @@ __device__ double invert4(const double m[4][4], double b[4][4]) {
 }
 
 // write metric, inverse (upper triangle), sqrt(-g) and lapse of one point
-__device__ void store_point(double x1, double x2, const grmhd_problem& p, double* dt, float* ft,
-                            int ts, int off, double gcon_out[4][4]) {
+__device__ void store_point(double x1, double x2, double x3, const grmhd_problem& p, double* dt, float* ft,
+                            size_t ts, int off, double gcon_out[4][4]) {
   double g[4][4], gi[4][4];
-  gcov_code(x1, x2, p, g);
+  gcov_code(x1, x2, x3, p, g);
   const double det = invert4(g, gi);
   for (int m = 0; m < 4; ++m)
     for (int n = m; n < 4; ++n) {
@@ -139,64 +170,67 @@ __device__ void store_point(double x1, double x2, const grmhd_problem& p, double
 __global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t) {
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - NG;
   const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y) - NG;
+  const int k = (int)blockIdx.z - NG;  // 2D tables: a single plane (k = -NG, tk = 0)
   if (i >= d.n1 + NG || j >= d.n2 + NG) return;
-  const int off = tab_of(d, j, i);
+  const int off = (k + NG) * d.tk + tab_of(d, j, i);
+  const size_t ts = (size_t)d.ts;
   const double dx1 = (p.x1max - p.x1min) / p.n1;
   const double dx2 = (p.x2max - p.x2min) / p.n2;
-  const double x1c = p.x1min + (i + 0.5) * dx1, x2c = p.x2min + (j + 0.5) * dx2;
-  const double x1f = p.x1min + i * dx1, x2f = p.x2min + j * dx2;
+  const double dx3 = (p.x3max - p.x3min) / p.n3;
+  const double x1c = p.x1min + (i + 0.5) * dx1, x2c = p.x2min + (j + 0.5) * dx2, x3c = p.x3min + (k + 0.5) * dx3;
+  const double x1f = p.x1min + i * dx1, x2f = p.x2min + j * dx2, x3f = p.x3min + k * dx3;
+  const bool k3 = p.coords == GRMHD_KERR_CKS;
 
   double gcon[4][4];
-  store_point(x1c, x2c, p, t.cent, t.centf, d.ts, off, gcon);
-  store_point(x1f, x2c, p, t.f1, t.f1f, d.ts, off, nullptr);
-  store_point(x1c, x2f, p, t.f2, t.f2f, d.ts, off, nullptr);
+  store_point(x1c, x2c, x3c, p, t.cent, t.centf, ts, off, gcon);
+  store_point(x1f, x2c, x3c, p, t.f1, t.f1f, ts, off, nullptr);
+  store_point(x1c, x2f, x3c, p, t.f2, t.f2f, ts, off, nullptr);
+  if (k3) store_point(x1c, x2c, x3f, p, t.f3, t.f3f, ts, off, nullptr);
 
   // connection: Gamma_kmn = (d_n g_km + d_m g_kn - d_k g_mn)/2, Gamma^l_mn = g^lk Gamma_kmn,
-  // derivatives by centred differences in x1 and x2 (d_t = d_x3 = 0)
-  double dg[3][4][4];  // dg[c-1][a][b] = d_c g_ab for c = 1, 2; index 2 unused (zero)
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) dg[2][a][b] = 0.0;
+  // derivatives by centred differences in x1, x2 and (3D tables) x3; d_t = 0
+  double dg[3][4][4];  // dg[c-1][a][b] = d_c g_ab, c = 1..3
+  for (int c = 0; c < 3; ++c)
+    for (int a = 0; a < 4; ++a)
+      for (int b = 0; b < 4; ++b) dg[c][a][b] = 0.0;
   if (p.coords != GRMHD_MINKOWSKI_CART) {
-    double gp[4][4], gm[4][4];
-    gcov_code(x1c + FD_DELTA, x2c, p, gp);
-    gcov_code(x1c - FD_DELTA, x2c, p, gm);
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) dg[0][a][b] = (gp[a][b] - gm[a][b]) / (2.0 * FD_DELTA);
-    gcov_code(x1c, x2c + FD_DELTA, p, gp);
-    gcov_code(x1c, x2c - FD_DELTA, p, gm);
-    for (int a = 0; a < 4; ++a)
-      for (int b = 0; b < 4; ++b) dg[1][a][b] = (gp[a][b] - gm[a][b]) / (2.0 * FD_DELTA);
-  } else {
-    for (int c = 0; c < 2; ++c)
+    const int nd = k3 ? 3 : 2;
+    for (int c = 0; c < nd; ++c) {
+      const double e1 = c == 0 ? FD_DELTA : 0.0, e2 = c == 1 ? FD_DELTA : 0.0, e3 = c == 2 ? FD_DELTA : 0.0;
+      double gp[4][4], gm[4][4];
+      gcov_code(x1c + e1, x2c + e2, x3c + e3, p, gp);
+      gcov_code(x1c - e1, x2c - e2, x3c - e3, p, gm);
       for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) dg[c][a][b] = 0.0;
+        for (int b = 0; b < 4; ++b) dg[c][a][b] = (gp[a][b] - gm[a][b]) / (2.0 * FD_DELTA);
+    }
   }
-  auto D = [&](int c, int a, int b) -> double { return (c == 1 || c == 2) ? dg[c - 1][a][b] : 0.0; };
+  auto D = [&](int c, int a, int b) -> double { return c > 0 ? dg[c - 1][a][b] : 0.0; };
   for (int l = 0; l < 4; ++l)
     for (int m = 0; m < 4; ++m)
       for (int n = m; n < 4; ++n) {
         double s = 0.0;
-        for (int k = 0; k < 4; ++k) s += gcon[l][k] * 0.5 * (D(n, k, m) + D(m, k, n) - D(k, m, n));
-        t.cent[(T_CONN + 10 * l + sidx(m, n)) * d.ts + off] = s;
+        for (int q = 0; q < 4; ++q) s += gcon[l][q] * 0.5 * (D(n, q, m) + D(m, q, n) - D(q, m, n));
+        t.cent[(T_CONN + 10 * l + sidx(m, n)) * ts + off] = s;
       }
 
-  // floor scales (Kerr: r = exp(x1))
+  // floor scales: k = 1/(r^2 (1 + r/10)) with r = exp(x1) (MKS / FMKS) or the
+  // Kerr-Schild radius of the Cartesian point
   double rfl = 0.0, ufl = 0.0;
   if (p.coords != GRMHD_MINKOWSKI_CART) {
-    const double r = exp(x1c);
-    const double k = 1.0 / (r * r * (1.0 + r / 10.0));
-    rfl = p.rho_fl * k;
-    ufl = p.u_fl * pow(k, p.gam);
+    const double r = k3 ? cks_r(x1c, x2c, x3c, p.a) : exp(x1c);
+    const double kk = 1.0 / (r * r * (1.0 + r / 10.0));
+    rfl = p.rho_fl * kk;
+    ufl = p.u_fl * pow(kk, p.gam);
   }
-  t.cent[T_RHOFL * d.ts + off] = rfl;
-  t.cent[T_UFL * d.ts + off] = ufl;
+  t.cent[T_RHOFL * ts + off] = rfl;
+  t.cent[T_UFL * ts + off] = ufl;
 }
 
 }  // namespace
 
 hipError_t launch_geometry(const grmhd_problem& p, const Dims& d, const Tables& t, hipStream_t s) {
   dim3 blk(64, 4, 1);
-  dim3 grd((d.n1 + 2 * NG + 63) / 64, (d.n2 + 2 * NG + 3) / 4, 1);
+  dim3 grd((d.n1 + 2 * NG + 63) / 64, (d.n2 + 2 * NG + 3) / 4, d.tk ? d.p3 : 1);
   hipLaunchKernelGGL(geometry_kernel, grd, blk, 0, s, p, d, t);
   return hipGetLastError();
 }

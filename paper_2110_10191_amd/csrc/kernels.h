@@ -6,13 +6,16 @@
 
 #include "common.h"
 
+// [N_CENT or N_FACE][p2][p1] (2D) or [..][p3][p2][p1] (3D, Dims::tk != 0)
 struct Tables {
-  double* cent;   // [N_CENT][p2][p1]
-  double* f1;     // [N_FACE][p2][p1]
+  double* cent;   // centre tables
+  double* f1;     // x1-, x2-, x3-face tables (f3 is cent for 2D tables)
   double* f2;
+  double* f3;
   float* centf;   // float copies of the first N_FACE components (mixed precision)
   float* f1f;
   float* f2f;
+  float* f3f;     // centf for 2D tables
 };
 
 // device counters kept by a context

@@ -46,7 +46,7 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
     }
   }
   Geo<T> g;
-  load_geo(g, tab, d.ts, tab_of(d, j, i));
+  load_geo(g, tab_plane(tab, d, k), d.ts, tab_of(d, j, i));
   T FL[NV], UL[NV], cpL, cmL;
   {
     Fluid<T> f;
@@ -92,7 +92,7 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
 // cells starting at (-1, -1, -1)
 template <int RECON, typename T>
 __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T* __restrict__ t1,
-                           const T* __restrict__ t2, const T* __restrict__ tc, T* __restrict__ F1, T* __restrict__ F2,
+                           const T* __restrict__ t2, const T* __restrict__ t3, T* __restrict__ F1, T* __restrict__ F2,
                            T* __restrict__ F3, T gam, int b, unsigned long long* ctop) {
   const TileK t = xcd_tile_k(b, d.stx, d.sty, d.n1 + 2, d.n3 + 2);
   const int i = -1 + t.i0 + (int)threadIdx.x;
@@ -102,7 +102,7 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
   double c1 = 0.0, c2 = 0.0, c3 = 0.0;
   if (ok && i >= 0) c1 = one_face<1, RECON, T>(d, P, t1, F1, gam, i, j, k);
   if (ok && j >= 0) c2 = one_face<2, RECON, T>(d, P, t2, F2, gam, i, j, k);
-  if (ok && k >= 0) c3 = one_face<3, RECON, T>(d, P, tc, F3, gam, i, j, k);
+  if (ok && k >= 0) c3 = one_face<3, RECON, T>(d, P, t3, F3, gam, i, j, k);
   if (ctop) {
     // three block reductions through the same shared scratch, one after another
     block_max_to(c1, ctop + 0);
@@ -115,10 +115,10 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
 
 template <int RECON, typename T>
 __global__ __launch_bounds__(512) void sweep_kernel(Dims d, const double* __restrict__ P, const T* __restrict__ t1,
-                                                    const T* __restrict__ t2, const T* __restrict__ tc,
+                                                    const T* __restrict__ t2, const T* __restrict__ t3,
                                                     T* __restrict__ F1, T* __restrict__ F2, T* __restrict__ F3, T gam,
                                                     unsigned long long* ctop) {
-  sweep_body<RECON, T>(d, P, t1, t2, tc, F1, F2, F3, gam, (int)blockIdx.x, ctop);
+  sweep_body<RECON, T>(d, P, t1, t2, t3, F1, F2, F3, gam, (int)blockIdx.x, ctop);
 }
 
 template <typename T>
@@ -127,13 +127,13 @@ template <>
 struct FaceTables<double> {
   __host__ __device__ static const double* f1(const Tables& t) { return t.f1; }
   __host__ __device__ static const double* f2(const Tables& t) { return t.f2; }
-  __host__ __device__ static const double* c(const Tables& t) { return t.cent; }
+  __host__ __device__ static const double* f3(const Tables& t) { return t.f3; }
 };
 template <>
 struct FaceTables<float> {
   __host__ __device__ static const float* f1(const Tables& t) { return t.f1f; }
   __host__ __device__ static const float* f2(const Tables& t) { return t.f2f; }
-  __host__ __device__ static const float* c(const Tables& t) { return t.centf; }
+  __host__ __device__ static const float* f3(const Tables& t) { return t.f3f; }
 };
 
 // every job of a batch in one grid; predictor sweeps P, corrector sweeps P_h
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(512) void sweep_batch_kernel(BatchView bv, int corr
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
   sweep_body<RECON, T>(J.d, global_ptr(corrector ? J.Ph : J.P), global_ptr(FaceTables<T>::f1(J.t)),
-                       global_ptr(FaceTables<T>::f2(J.t)), global_ptr(FaceTables<T>::c(J.t)),
+                       global_ptr(FaceTables<T>::f2(J.t)), global_ptr(FaceTables<T>::f3(J.t)),
                        global_ptr((T*)J.F[0]), global_ptr((T*)J.F[1]), global_ptr((T*)J.F[2]), (T)J.p.gam,
                        (int)blockIdx.x - offs[jb], want_ctop ? global_ptr(J.ctr->ctop) : nullptr);
 }
@@ -153,7 +153,7 @@ void launch_for(const Dims& d, const Tables& t, double gam, const double* P, voi
                 hipStream_t s) {
   const unsigned nblk = sweep_blocks(d);
   hipLaunchKernelGGL((sweep_kernel<RECON, T>), dim3(nblk), dim3(d.stx, d.sty, 1), 0, s, d, P, FaceTables<T>::f1(t),
-                     FaceTables<T>::f2(t), FaceTables<T>::c(t), (T*)F[0], (T*)F[1], (T*)F[2], (T)gam, ctop);
+                     FaceTables<T>::f2(t), FaceTables<T>::f3(t), (T*)F[0], (T*)F[1], (T*)F[2], (T)gam, ctop);
 }
 
 }  // namespace

@@ -211,8 +211,9 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
     }
 
     const int toff = tab_of(d, j, i);
+    const double* ck = tab_plane(cent, d, k);
     Geo<double> g;
-    load_geo(g, cent, d.ts, toff);
+    load_geo(g, ck, d.ts, toff);
     if (!EARLY_PS) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) ps[v] = Ps[v * d.sv + c];
@@ -233,7 +234,7 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-          for (int l = 0; l < 4; ++l) sacc += T[kk][l] * cent[(T_CONN + 10 * l + sidx(nu, kk)) * d.ts + toff];
+          for (int l = 0; l < 4; ++l) sacc += T[kk][l] * ck[(T_CONN + 10 * l + sidx(nu, kk)) * d.ts + toff];
         rhs[1 + nu] += g.gdet * sacc;
       }
     }
@@ -250,7 +251,7 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
     for (int v = 0; v < NV; ++v) U[v] = U[v] + dt * rhs[v];
     double pn[NV];
     failed = invert_1dw(U, ps, g, up.gam, pn) ? 1 : 0;
-    if (up.floors) apply_floors(pn, g, cent[T_RHOFL * d.ts + toff], cent[T_UFL * d.ts + toff], up);
+    if (up.floors) apply_floors(pn, g, ck[T_RHOFL * d.ts + toff], ck[T_UFL * d.ts + toff], up);
 #pragma unroll
     for (int v = 0; v < NV; ++v) Pout[v * d.sv + c] = pn[v];
     flags[c] = (int8_t)failed;
@@ -341,9 +342,10 @@ __device__ void fixup_body(const Dims& d, const double* __restrict__ cent, const
     for (int v = 0; v < 5; ++v) pn[v] = acc[v] / cnt;
   if (up.floors) {
     const int toff = tab_of(d, j, i);
+    const double* ck = tab_plane(cent, d, k);
     Geo<double> g;
-    load_geo(g, cent, d.ts, toff);
-    apply_floors(pn, g, cent[T_RHOFL * d.ts + toff], cent[T_UFL * d.ts + toff], up);
+    load_geo(g, ck, d.ts, toff);
+    apply_floors(pn, g, ck[T_RHOFL * d.ts + toff], ck[T_UFL * d.ts + toff], up);
   }
   bool fin = true;
   for (int v = 0; v < 5; ++v) {
@@ -375,7 +377,7 @@ __global__ __launch_bounds__(256) void p2u_kernel(Dims d, const double* __restri
   if (i >= d.n1 || j >= d.n2) return;
   const int c = cell_of(d, k, j, i);
   Geo<double> g;
-  load_geo(g, cent, d.ts, tab_of(d, j, i));
+  load_geo(g, tab_plane(cent, d, k), d.ts, tab_of(d, j, i));
   double p[NV], u[NV];
   for (int v = 0; v < NV; ++v) p[v] = P[v * d.sv + c];
   Fluid<double> f;
@@ -394,15 +396,16 @@ __global__ __launch_bounds__(256) void u2p_kernel(Dims d, const double* __restri
   if (i < d.n1 && j < d.n2) {
     const int c = cell_of(d, k, j, i);
     const int toff = tab_of(d, j, i);
+    const double* ck = tab_plane(cent, d, k);
     Geo<double> g;
-    load_geo(g, cent, d.ts, toff);
+    load_geo(g, ck, d.ts, toff);
     double u[NV], guess[NV], pn[NV];
     for (int v = 0; v < NV; ++v) {
       u[v] = U[v * d.sv + c];
       guess[v] = P[v * d.sv + c];
     }
     failed = invert_1dw(u, guess, g, up.gam, pn) ? 1 : 0;
-    if (up.floors) apply_floors(pn, g, cent[T_RHOFL * d.ts + toff], cent[T_UFL * d.ts + toff], up);
+    if (up.floors) apply_floors(pn, g, ck[T_RHOFL * d.ts + toff], ck[T_UFL * d.ts + toff], up);
     for (int v = 0; v < NV; ++v) P[v * d.sv + c] = pn[v];
     flags[c] = (int8_t)failed;
   }

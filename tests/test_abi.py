@@ -160,3 +160,31 @@ def test_context_bytes_without_a_device(lib):
     bad = dict(prm, n1=0)
     with pytest.raises(lib.GrmhdError):
         lib.grmhd_context_bytes(bad)
+
+
+def test_cartesian_kerr_schild_tables_are_3d(lib):
+    prm, _ = problems.cks_bondi(24, 20, 16)
+    cb, sb = lib.grmhd_context_bytes(prm)
+    n1p = -(-(24 + 6) // 8) * 8
+    cells = (16 + 6) * (20 + 6) * n1p
+    assert sb == 8 * 8 * cells
+    tables = (64 + 3 * 22) * 8 * cells + 4 * 22 * 4 * cells      # 3D, with x3-face tables
+    scratch = 8 * 8 * cells + 3 * 8 * 8 * cells + cells       # half-step state, fluxes, flags
+    assert tables + scratch <= cb <= tables + scratch + 4096
+
+
+@pytest.mark.parametrize("edit,needle", [
+    (dict(bc=[[1, 1], [3, 3], [3, 3]]), "periodic or Dirichlet"),
+    (dict(bc=[[3, 3], [2, 2], [3, 3]]), "periodic or Dirichlet"),
+    (dict(x1min=-0.5, x1max=0.5, x2min=-0.5, x2max=0.5, x3min=-0.5, x3max=0.5), "unit sphere"),
+    (dict(x1min=1.2, x1max=3.0, x2min=-0.5, x2max=0.5, x3min=-0.5, x3max=0.5), "unit sphere"),
+    (dict(n1=330, n2=330, n3=330), "3D geometry tables"),
+    (dict(a=1.0), "|a| < 1"),
+])
+def test_cartesian_kerr_schild_validation(lib, edit, needle):
+    prm, _ = problems.cks_bondi(12, 10, 8)
+    prm = dict(prm)
+    prm.update(edit)
+    with pytest.raises(lib.GrmhdError):
+        lib.grmhd_context_bytes(prm)
+    assert needle in lib.grmhd_last_error(None)
