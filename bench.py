@@ -28,6 +28,10 @@ few steps of the 64-job batched workload against the per-job FP64 loop
 (``many``), and the oracle (NumPy FP64, one core) timed on a bounded sample of
 the same torus.
 
+``--coords cks`` times another workload instead: a magnetised Michel flow on a
+168^3 Cartesian Kerr-Schild box, whose geometry tables are 3D (every zone
+reads its own metric and connection, 2400 B per zone-cycle compulsory).
+
 Prints one JSON line on stdout.
 """
 
@@ -44,6 +48,7 @@ HBM_PEAK = 8.0e12          # bytes/s, MI355X HBM3E
 FP64_PEAK = 78.6e12        # flop/s, MI355X FP64 vector
 FP32_PEAK = 157.3e12       # flop/s, MI355X FP32 vector
 NG = 3
+CKS = 3                    # Cartesian Kerr-Schild coordinates
 
 
 def compulsory_bytes_per_zone_cycle(prm):
@@ -51,7 +56,14 @@ def compulsory_bytes_per_zone_cycle(prm):
     step reads P^n and writes P_h (predictor), reads P^n and P_h and writes
     P^{n+1} (corrector), 5 x 64 = 320 B a zone; plus, on a Kerr grid, the
     axisymmetric geometry, about 150 doubles per (x1, x2) column per substep,
-    shared by the n3 zones of the column. 338.75 B on the 288 x 128 x 128 torus."""
+    shared by the n3 zones of the column. 338.75 B on the 288 x 128 x 128 torus.
+    Cartesian Kerr-Schild geometry depends on x3, so every zone reads its own
+    tables each substep: the centre table (64 values: metric, inverse,
+    sqrt(-g), lapse, connection, floor scales) and three face tables (22
+    values each; float in mixed precision)."""
+    if prm["coords"] == CKS:
+        face = 4 if prm["precision"] == 1 else 8
+        return 320.0 + 2 * (64 * 8 + 3 * 22 * face)
     geo = 0.0 if prm["coords"] == 0 else 2 * 150 * 8 / prm["n3"]
     return 320.0 + geo
 
@@ -72,7 +84,7 @@ def split_design_bytes(kernel, prm, mixed):
         cells = (n1 + 2 * recon_reach) * (n2 + 2 * recon_reach) * (n3 + 2 * recon_reach)
         faces = ((n1 + 1) * (n2 + 2) * (n3 + 2) + (n1 + 2) * (n2 + 1) * (n3 + 2)
                  + (n1 + 2) * (n2 + 2) * (n3 + 1))
-        geo = 3 * 22 * fb * (n1 + 2) * (n2 + 2)
+        geo = 3 * 22 * fb * (n1 + 2) * (n2 + 2) * ((n3 + 2) if prm["coords"] == CKS else 1)
         return 64 * cells + 7 * fb * faces + geo
     if kernel == "update":
         zones = n1 * n2 * n3
@@ -80,7 +92,7 @@ def split_design_bytes(kernel, prm, mixed):
         # read: one in the predictor (P_base = P_s = P), two in the corrector
         # (P, P_h), 96 B a zone on average over the two launches of a step;
         # P_out written; one flag byte; the 2D centre table once
-        return zones * (21 * fb + 96 + 64 + 1) + 64 * 8 * n1 * n2
+        return zones * (21 * fb + 96 + 64 + 1) + 64 * 8 * n1 * n2 * (n3 if prm["coords"] == CKS else 1)
     raise KeyError(kernel)
 
 
@@ -172,6 +184,24 @@ def cpu_baseline(prm_full, nslabs=32, nsteps=2):
                    f"({zones} zones, same per-zone work as the benchmark grid) in {secs:.1f} s; "
                    "NumPy element-wise, single thread"),
     }
+
+
+def cpu_baseline_cks(prm_full, nsteps=2):
+    """The oracle on a 48^3 Cartesian Kerr-Schild box of the same flow."""
+    import oracle
+    import problems
+    prm, P0 = problems.cks_bondi(48, 48, 48, recon=prm_full["recon"])
+    g = oracle.Grid(prm)
+    dt = oracle.get_dt(P0, g)
+    P = P0
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        P, _, _ = oracle.step(P, g, dt)
+    secs = time.perf_counter() - t0
+    zones = 48 ** 3
+    return {"value": zones * nsteps / secs, "unit": "zone-cycles/s", "cores": 1,
+            "host_os_cpu_count": os.cpu_count(), "kind": "oracle",
+            "sample": f"{nsteps} FP64 steps of a 48^3 Cartesian Kerr-Schild box of the same flow in {secs:.1f} s"}
 
 
 def many_record(steps, warmup, tune_tiles):
@@ -285,7 +315,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--recon", choices=["mc", "weno5"], default="mc")
-    ap.add_argument("--grid", type=int, nargs=3, default=[288, 128, 128])
+    ap.add_argument("--grid", type=int, nargs=3, default=None,
+                    help="zones (default 288 128 128 for the torus, 168 168 168 for --coords cks)")
+    ap.add_argument("--coords", choices=["fmks", "cks"], default="fmks",
+                    help="fmks: the torus (default); cks: a magnetised Michel flow on a Cartesian "
+                         "Kerr-Schild box (3D geometry tables), a workload of its own")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-many", action="store_true",
                     help="leave out the 64-job batched-vs-loop sub-record of the torus line")
@@ -319,10 +353,14 @@ def main():
 
     recon = problems.RECON_MC if args.recon == "mc" else problems.RECON_WENO5
     mixed = args.precision == "mixed"
-    n1, n2, n3 = args.grid
+    cks = args.coords == "cks"
+    n1, n2, n3 = args.grid or ([168, 168, 168] if cks else [288, 128, 128])
     t_gen = time.perf_counter()
-    prm, P0 = problems.fm_torus(n1=n1, n2=n2, n3=n3, recon=recon,
-                                precision=problems.MIXED if mixed else problems.FP64)
+    prec = problems.MIXED if mixed else problems.FP64
+    if cks:
+        prm, P0 = problems.cks_bondi(n1, n2, n3, recon=recon, precision=prec)
+    else:
+        prm, P0 = problems.fm_torus(n1=n1, n2=n2, n3=n3, recon=recon, precision=prec)
     print(f"[bench] initial data {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
@@ -387,7 +425,7 @@ def main():
     per_zc = compulsory_bytes_per_zone_cycle(prm)
     per_launch = per_zc * zones / 2
     achieved = per_launch / t_launch
-    workload = f"fm_torus_{n1}x{n2}x{n3}_{args.recon}_{args.precision}"
+    workload = f"{'cks_bondi' if cks else 'fm_torus'}_{n1}x{n2}x{n3}_{args.recon}_{args.precision}"
     if args.electrons:
         workload += f"_electrons_{args.electrons}"
     traffic = measured_traffic(workload)
@@ -398,7 +436,9 @@ def main():
                 "kernel": dom, "mean_launch_ms": ms / n,
                 "algorithmic_bytes_per_launch": per_launch,
                 "algorithmic_basis": (f"{per_zc:.2f} B per zone-cycle (P^n, P_h, P^n+1 traffic of the two substeps "
-                                      f"plus the 2D geometry over n3) x {zones} zones / 2 (one substep)")}
+                                      + ("plus the 3D geometry tables of every zone" if cks else
+                                         "plus the 2D geometry over n3")
+                                      + f") x {zones} zones / 2 (one substep)")}
     if traffic:
         step_traffic = sum(rec["bytes_per_launch"] * rec["launches_per_step"] for rec in traffic.values())
         roofline["traffic_ratio"] = {
@@ -472,7 +512,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload,
                    "grid": [n1, n2, n3], "a": prm["a"], "recon": args.recon,
-                   "precision": args.precision, "coords": "fmks", "r_out": 1000.0,
+                   "precision": args.precision, "coords": args.coords,
+                   **({"box": [[prm["x1min"], prm["x1max"]], [prm["x2min"], prm["x2max"]],
+                               [prm["x3min"], prm["x3max"]]]} if cks else {"r_out": 1000.0}),
                    "driver": args.path,
                    "electrons": args.electrons},
         "repeats": {"n": nrep, "steps": reps, "zone_cycles_per_s": rep_rates,
@@ -484,13 +526,13 @@ def main():
     sim.close()
     del P
     torch.cuda.empty_cache()
-    if not args.no_many and not args.electrons:
+    if not args.no_many and not args.electrons and not cks:
         # the batched form against the per-job FP64 loop, a few steps of the
         # 64-job mix with tuned batch tiles
         out["many"] = many_record(args.many_steps, 1, True)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(prm)
+        out["cpu_baseline"] = cpu_baseline_cks(prm) if cks else cpu_baseline(prm)
     print(json.dumps(out), flush=True)
 
 
