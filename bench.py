@@ -25,8 +25,9 @@ state traffic of a step plus the 2D geometry, 338.75 B per zone-cycle on the
 benchmark torus) for the zone-cycles one launch advances; this design's own
 byte model (face fluxes included) is a separate view. The line also carries a
 few steps of the 64-job batched workload against the per-job FP64 loop
-(``many``), and the oracle (NumPy FP64, one core) timed on a bounded sample of
-the same torus.
+(``many``), the serving loop's p50 / p99 job latency on a short Poisson stream
+of uneven jobs (``serving``), and the oracle (NumPy FP64, one core) timed on a
+bounded sample of the same torus.
 
 ``--coords cks`` times another workload instead: a magnetised Michel flow on a
 168^3 Cartesian Kerr-Schild box, whose geometry tables are 3D (every zone
@@ -204,6 +205,37 @@ def cpu_baseline_cks(prm_full, nsteps=2):
             "sample": f"{nsteps} FP64 steps of a 48^3 Cartesian Kerr-Schild box of the same flow in {secs:.1f} s"}
 
 
+def serving_record(n_jobs=48, lam=7.0, seed=4, steps=(100, 400), identity=2):
+    """The serving loop (``paper_2110_10191_amd.serve``) on a short Poisson
+    stream of torus and Kerr Bondi jobs of uneven grids (WENO5, mixed
+    precision, continuous batching under a 200 GB budget): job latency from
+    arrival to completion (p50 / p99), queueing wait, and zone-cycles/s over the
+    makespan, with the offered rate for comparison; a few jobs are re-run
+    alone and must be bitwise equal to their results in the mix."""
+    import numpy as np
+    import problems
+    from problems.workloads import poisson_stream
+    from paper_2110_10191_amd import serve
+    recon, precision = problems.RECON_WENO5, problems.MIXED
+    specs = poisson_stream(n_jobs, lam, seed, steps=steps)
+
+    def make_state(spec):
+        return spec.make(recon=recon, precision=precision)
+
+    rng = np.random.default_rng(seed + 1000)
+    sample = sorted(int(x) for x in rng.choice(len(specs), size=identity, replace=False))
+    eng = serve.GpuEngine(recon, precision)
+    srv = serve.Server(eng, make_state, int(200e9), quantum=25, keep=sample)
+    rep = srv.run(specs)
+    summ = rep.summary()
+    ident = serve.identity_check(rep, specs, make_state, recon, precision, sample)
+    summ["identity_alone_vs_mix"] = {str(k): v for k, v in ident.items()}
+    summ["config"] = {"workload": f"poisson stream of {n_jobs} torus / Kerr Bondi jobs (64-192 x 64-128 x 32-64)",
+                      "lam_per_s": lam, "seed": seed, "steps": list(steps), "recon": "weno5",
+                      "precision": "mixed", "budget_gb": 200.0, "quantum": 25}
+    return summ
+
+
 def many_record(steps, warmup, tune_tiles):
     """64 independent uneven jobs (32 periodic boxes N^3, N in 32..96; 32 Bondi
     flows in Kerr, a ~ U[0, 0.99], up to 192 x 128 x 64): every job advanced
@@ -324,6 +356,8 @@ def main():
     ap.add_argument("--no-many", action="store_true",
                     help="leave out the 64-job batched-vs-loop sub-record of the torus line")
     ap.add_argument("--many-steps", type=int, default=5, help="timed steps of the 64-job sub-record")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="leave out the serving sub-record (p50/p99 job latency of a short Poisson stream)")
     ap.add_argument("--workload", choices=["torus", "many"], default="torus",
                     help="torus: one large torus (default); many: 64 uneven jobs batched vs looped")
     ap.add_argument("--tune", action="store_true", help="autotune the batch tiles (workload many)")
@@ -530,6 +564,9 @@ def main():
         # the batched form against the per-job FP64 loop, a few steps of the
         # 64-job mix with tuned batch tiles
         out["many"] = many_record(args.many_steps, 1, True)
+    if not args.no_serving and not args.electrons and not cks:
+        print("[bench] serving stream", file=sys.stderr, flush=True)
+        out["serving"] = serving_record()
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline_cks(prm) if cks else cpu_baseline(prm)
