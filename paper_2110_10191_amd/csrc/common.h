@@ -110,9 +110,26 @@ __device__ inline T lorentz_sq(const T* gcov, T v1, T v2, T v3) {
          T(2) * (gcov[5] * v1 * v2 + gcov[6] * v1 * v3 + gcov[8] * v2 * v3);
 }
 
-template <typename T>
+// 1/sqrt(x) to full precision: the hardware estimate, then Newton steps
+__device__ inline double rsqrt_full(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r * (1.5 - 0.5 * x * r * r);
+}
+__device__ inline float rsqrt_full(float x) {
+  const float r = __builtin_amdgcn_rsqf(x);
+  return r * (1.5f - 0.5f * x * r * r);
+}
+
+// the fluid four-vectors of primitives P. RSQ: Gamma and 1/u^t from one
+// reciprocal square root (Gamma = G2 / sqrt(G2), 1/u^t = alpha / Gamma) instead
+// of a square root and a division (the face-flux pass, where it is faster;
+// the update keeps the plain form, whose register allocation it suits)
+template <typename T, bool RSQ = false>
 __device__ inline void fluid_state(const T* P, const Geo<T>& g, T gam, Fluid<T>& f) {
-  const T lor = sqrt(lorentz_sq(g.gcov, P[2], P[3], P[4]));
+  const T l2 = lorentz_sq(g.gcov, P[2], P[3], P[4]);
+  const T rl = RSQ ? rsqrt_full(l2) : T(0);
+  const T lor = RSQ ? l2 * rl : sqrt(l2);
   f.ucon[0] = lor / g.alpha;
   const T la = lor * g.alpha;
   f.ucon[1] = P[2] - la * g.gcon[1];
@@ -121,7 +138,7 @@ __device__ inline void fluid_state(const T* P, const Geo<T>& g, T gam, Fluid<T>&
 #pragma unroll
   for (int m = 0; m < 4; ++m) f.ucov[m] = lower(g.gcov, f.ucon, m);
   const T bt = P[5] * f.ucov[1] + P[6] * f.ucov[2] + P[7] * f.ucov[3];
-  const T iut = T(1) / f.ucon[0];
+  const T iut = RSQ ? g.alpha * rl : T(1) / f.ucon[0];
   f.bcon[0] = bt;
   f.bcon[1] = (P[5] + bt * f.ucon[1]) * iut;
   f.bcon[2] = (P[6] + bt * f.ucon[2]) * iut;
@@ -160,14 +177,16 @@ __device__ inline void flux_of(const T* P, const Fluid<T>& f, T gdet, T* F) {
 
 // Fast-magnetosonic speeds dx^D/dt: roots of A l^2 + B l + C = 0 with
 // c^2 = v_A^2 + c_s^2 (1 - v_A^2), v_A^2 = b^2/(b^2 + w), c_s^2 = gamma p / w,
-// evaluated as the equal single quotient (b^2 + gamma p)/(b^2 + w).
+// which is the single quotient num/den = (b^2 + gamma p)/(b^2 + w); A, B and C
+// are taken times den > 0, which leaves the roots unchanged and saves the
+// division.
 template <int D, typename T>
 __device__ inline void signal_speeds(const Fluid<T>& f, const Geo<T>& g, T gam, T& cmax, T& cmin) {
-  const T c2 = (f.bsq + gam * f.p) / (f.bsq + f.w);
+  const T num = f.bsq + gam * f.p, den = f.bsq + f.w;
   const T ut = f.ucon[0], ud = f.ucon[D];
-  const T A = ut * ut - c2 * (g.gcon[0] + ut * ut);
-  const T B = T(-2) * (ut * ud - c2 * (g.gcon[D] + ut * ud));
-  const T C = ud * ud - c2 * (g.gcon[sidx(D, D)] + ud * ud);
+  const T A = den * ut * ut - num * (g.gcon[0] + ut * ut);
+  const T B = T(-2) * (den * ut * ud - num * (g.gcon[D] + ut * ud));
+  const T C = den * ud * ud - num * (g.gcon[sidx(D, D)] + ud * ud);
   const T disc = sqrt(fmax(B * B - T(4) * A * C, T(0)));
   const T i2a = T(1) / (T(2) * A);
   const T vp = (-B + disc) * i2a;

@@ -50,7 +50,7 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
   T FL[NV], UL[NV], cpL, cmL;
   {
     Fluid<T> f;
-    fluid_state(PL, g, gam, f);
+    fluid_state<T, true>(PL, g, gam, f);
     flux_of<D>(PL, f, g.gdet, FL);
     flux_of<0>(PL, f, g.gdet, UL);
     signal_speeds<D>(f, g, gam, cpL, cmL);
@@ -58,7 +58,7 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
   T FR[NV], UR[NV], cpR, cmR;
   {
     Fluid<T> f;
-    fluid_state(PR, g, gam, f);
+    fluid_state<T, true>(PR, g, gam, f);
     flux_of<D>(PR, f, g.gdet, FR);
     flux_of<0>(PR, f, g.gdet, UR);
     signal_speeds<D>(f, g, gam, cpR, cmR);
