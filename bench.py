@@ -120,16 +120,16 @@ def device_copy_bandwidth(torch, dev, gib=1.0, reps=5):
 
 def measured_traffic(workload):
     """HBM bytes per launch of each kernel class from the committed counter
-    summary (profiles/hbm_traffic.json: FETCH_SIZE and WRITE_SIZE scaled by a
-    plain copy), with launches per step, only while the library is the build
-    those counters were taken on."""
+    summary (profiles/hbm_traffic.json, per workload: FETCH_SIZE and
+    WRITE_SIZE scaled by a plain copy), with launches per step, only while the
+    library is the build those counters were taken on."""
     path = os.path.join(HERE, "profiles", "hbm_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
         from paper_2110_10191_amd import tune
-        if rec.get("workload") == workload and rec.get("library_hash") == tune.library_hash():
-            return rec["kernels"]
+        if rec.get("library_hash") == tune.library_hash() and workload in rec.get("workloads", {}):
+            return rec["workloads"][workload]["kernels"]
     except (OSError, ValueError, KeyError):
         pass
     return None
