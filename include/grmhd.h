@@ -301,7 +301,7 @@ GRMHD_API int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_m
  * update and fixup kernels (GRMHD_TILE_UPDATE): tx zones along x1 by ty along
  * x2, one thread per zone (the face-flux kernel computes up to the three
  * lower faces of its zone); tx a power of two in [16, 256], tx * ty a multiple
- * of 64 and at most 512 (sweeps) or 256 (update). Defaults: sweeps 128 x 4,
+ * of 64 and at most 512 (sweeps) or 256 (update). Defaults: sweeps 64 x 8,
  * update 64 x 4. Results do not depend on the tile. A batch uses the tiles of
  * its first job for every job. Errors: EINVAL. */
 enum { GRMHD_TILE_SWEEP = 0, GRMHD_TILE_UPDATE = 1 };

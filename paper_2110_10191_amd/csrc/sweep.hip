@@ -11,11 +11,16 @@
 // transverse directions (the extra transverse layer feeds the Flux-CT EMFs).
 // One thread per cell (i, j, k) with i, j, k in [-1, n] computes the faces of
 // every direction whose range holds it, so a cell's primitives are read from
-// HBM once for the three directions and one launch replaces three. The
+// HBM once for the three directions and one launch replaces three. A block
+// first copies its tile of the x3 plane, with the reconstruction halo in x1
+// and x2, into LDS (coalesced along x1); the x1 and x2 stencils then come
+// from LDS and only the x3 stencil from the state. The
 // per-direction maximum of ctop over the faces with interior transverse index
 // feeds the Courant step (one atomic max per block and direction); a face with
 // a NaN speed counts as +inf there, which the step reports as a non-finite
 // state.
+#include <atomic>
+
 #include "kernels.h"
 
 namespace {
@@ -25,22 +30,40 @@ namespace {
 // zero and nothing reads) and return the signal speed for the Courant maximum
 // (0 for a face with a transverse ghost index, +inf when its speeds are not
 // finite)
+// the block's x3 plane of primitives with the stencil halo in x1 and x2,
+// [8][lh][lw] of T, cells (ib + li, jb + lj)
+template <typename T>
+struct PlaneTile {
+  const T* lds;
+  int lw, lh;    // row length and rows
+  int li, lj;    // this thread's cell in the tile
+  int plane;     // lw * lh
+};
+
+// halo of the reconstruction: zones below / above the cell (MC 2 / 1, WENO5 3 / 2)
+template <int RECON>
+constexpr int halo_lo() { return RECON == GRMHD_RECON_MC ? 2 : 3; }
+template <int RECON>
+constexpr int halo_hi() { return RECON == GRMHD_RECON_MC ? 1 : 2; }
+
 template <int D, int RECON, typename T>
-__device__ inline double one_face(const Dims& d, const double* __restrict__ P, const T* __restrict__ tab,
-                                  T* __restrict__ F, T gam, int i, int j, int k) {
+__device__ inline double one_face(const Dims& d, const double* __restrict__ P, const PlaneTile<T>& pt,
+                                  const T* __restrict__ tab, T* __restrict__ F, T gam, int i, int j, int k) {
   const int c = cell_of(d, k, j, i);
-  const int st = (D == 1) ? 1 : ((D == 2) ? d.s2 : d.s3);
   T PL[NV], PR[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    const double* q = P + v * d.sv + c;
+    // x1 and x2 stencils from the LDS tile, x3 from the state
+    const T* ql = pt.lds + v * pt.plane + pt.lj * pt.lw + pt.li;
+    const double* qg = P + v * d.sv + c;
+    const int st = (D == 1) ? 1 : pt.lw;
+    auto at = [&](int o) -> T { return D == 3 ? (T)qg[o * d.s3] : ql[o * st]; };
     if (RECON == GRMHD_RECON_MC) {
-      const T a = (T)q[-2 * st], bb = (T)q[-st], e = (T)q[0], f = (T)q[st];
+      const T a = at(-2), bb = at(-1), e = at(0), f = at(1);
       PL[v] = bb + T(0.5) * mc_slope(a, bb, e);
       PR[v] = e - T(0.5) * mc_slope(bb, e, f);
     } else {
-      const T x0 = (T)q[-3 * st], x1 = (T)q[-2 * st], x2 = (T)q[-st], x3 = (T)q[0],
-              x4 = (T)q[st], x5 = (T)q[2 * st];
+      const T x0 = at(-3), x1 = at(-2), x2 = at(-1), x3 = at(0), x4 = at(1), x5 = at(2);
       PL[v] = weno5_edge(x0, x1, x2, x3, x4);
       PR[v] = weno5_edge(x5, x4, x3, x2, x1);
     }
@@ -99,10 +122,36 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
   const int j = -1 + t.j0 + (int)threadIdx.y;
   const int k = -1 + t.k;
   const bool ok = t.valid && i <= d.n1 && j <= d.n2;
+  // stage this x3 plane of the tile and its x1 / x2 halo in LDS, once for the
+  // block: cells [ib, ib + lw) x [jb, jb + lh), those inside the padded state
+  // (cells outside it are never read: faces start at cell 0 and end at n)
+  extern __shared__ __align__(16) unsigned char sweep_lds[];
+  PlaneTile<T> pt;
+  pt.lds = reinterpret_cast<const T*>(sweep_lds);
+  pt.lw = d.stx + halo_lo<RECON>() + halo_hi<RECON>();
+  pt.lh = d.sty + halo_lo<RECON>() + halo_hi<RECON>();
+  pt.plane = pt.lw * pt.lh;
+  pt.li = (int)threadIdx.x + halo_lo<RECON>();
+  pt.lj = (int)threadIdx.y + halo_lo<RECON>();
+  if (t.valid) {
+    T* L = reinterpret_cast<T*>(sweep_lds);
+    const int ib = -1 + t.i0 - halo_lo<RECON>(), jb = -1 + t.j0 - halo_lo<RECON>();
+    const int nthr = d.stx * d.sty;
+    for (int e = (int)threadIdx.y * d.stx + (int)threadIdx.x; e < pt.plane; e += nthr) {
+      const int lj = e / pt.lw, li = e - lj * pt.lw;
+      const int gi = ib + li, gj = jb + lj;
+      if (gi >= -NG && gi < d.n1 + NG && gj >= -NG && gj < d.n2 + NG) {
+        const int c = cell_of(d, k, gj, gi);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) L[v * pt.plane + e] = (T)P[v * d.sv + c];
+      }
+    }
+  }
+  __syncthreads();
   double c1 = 0.0, c2 = 0.0, c3 = 0.0;
-  if (ok && i >= 0) c1 = one_face<1, RECON, T>(d, P, t1, F1, gam, i, j, k);
-  if (ok && j >= 0) c2 = one_face<2, RECON, T>(d, P, t2, F2, gam, i, j, k);
-  if (ok && k >= 0) c3 = one_face<3, RECON, T>(d, P, t3, F3, gam, i, j, k);
+  if (ok && i >= 0) c1 = one_face<1, RECON, T>(d, P, pt, t1, F1, gam, i, j, k);
+  if (ok && j >= 0) c2 = one_face<2, RECON, T>(d, P, pt, t2, F2, gam, i, j, k);
+  if (ok && k >= 0) c3 = one_face<3, RECON, T>(d, P, pt, t3, F3, gam, i, j, k);
   if (ctop) {
     // three block reductions through the same shared scratch, one after another
     block_max_to(c1, ctop + 0);
@@ -149,11 +198,46 @@ __global__ __launch_bounds__(512) void sweep_batch_kernel(BatchView bv, int corr
 }
 
 template <int RECON, typename T>
-void launch_for(const Dims& d, const Tables& t, double gam, const double* P, void* const* F, unsigned long long* ctop,
-                hipStream_t s) {
+size_t tile_bytes(int stx, int sty) {
+  return (size_t)NV * (stx + halo_lo<RECON>() + halo_hi<RECON>()) * (sty + halo_lo<RECON>() + halo_hi<RECON>()) *
+         sizeof(T);
+}
+
+// A kernel may use more dynamic LDS than the default 64 KiB only once the
+// limit is raised for it; the largest limit set so far is kept per kernel.
+template <auto KERNEL>
+hipError_t allow_lds(size_t bytes) {
+  static std::atomic<size_t> allowed{65536};
+  if (bytes <= allowed.load()) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute((const void*)KERNEL, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) {
+    size_t cur = allowed.load();
+    while (cur < bytes && !allowed.compare_exchange_weak(cur, bytes)) {
+    }
+  }
+  return e;
+}
+
+template <int RECON, typename T>
+hipError_t launch_for(const Dims& d, const Tables& t, double gam, const double* P, void* const* F,
+                      unsigned long long* ctop, hipStream_t s) {
   const unsigned nblk = sweep_blocks(d);
-  hipLaunchKernelGGL((sweep_kernel<RECON, T>), dim3(nblk), dim3(d.stx, d.sty, 1), 0, s, d, P, FaceTables<T>::f1(t),
-                     FaceTables<T>::f2(t), FaceTables<T>::f3(t), (T*)F[0], (T*)F[1], (T*)F[2], (T)gam, ctop);
+  const size_t lds = tile_bytes<RECON, T>(d.stx, d.sty);
+  const hipError_t e = allow_lds<sweep_kernel<RECON, T>>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((sweep_kernel<RECON, T>), dim3(nblk), dim3(d.stx, d.sty, 1), lds, s, d, P,
+                     FaceTables<T>::f1(t), FaceTables<T>::f2(t), FaceTables<T>::f3(t), (T*)F[0], (T*)F[1],
+                     (T*)F[2], (T)gam, ctop);
+  return hipGetLastError();
+}
+
+template <int RECON, typename T>
+hipError_t launch_batch_for(const BatchView& bv, dim3 grd, dim3 blk, int c, int w, hipStream_t s) {
+  const size_t lds = tile_bytes<RECON, T>(bv.stx, bv.sty);
+  const hipError_t e = allow_lds<sweep_batch_kernel<RECON, T>>(lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((sweep_batch_kernel<RECON, T>), grd, blk, lds, s, bv, c, w);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -163,13 +247,11 @@ unsigned sweep_blocks(const Dims& d) { return xcd_grid(d.n1 + 2, d.n2 + 2, d.n3 
 hipError_t launch_sweeps(int recon, bool mixed, const Dims& d, const Tables& t, double gam, const double* P,
                          void* const* F, unsigned long long* ctop, hipStream_t s) {
   if (mixed) {
-    if (recon == GRMHD_RECON_MC) launch_for<GRMHD_RECON_MC, float>(d, t, gam, P, F, ctop, s);
-    else launch_for<GRMHD_RECON_WENO5, float>(d, t, gam, P, F, ctop, s);
-  } else {
-    if (recon == GRMHD_RECON_MC) launch_for<GRMHD_RECON_MC, double>(d, t, gam, P, F, ctop, s);
-    else launch_for<GRMHD_RECON_WENO5, double>(d, t, gam, P, F, ctop, s);
+    if (recon == GRMHD_RECON_MC) return launch_for<GRMHD_RECON_MC, float>(d, t, gam, P, F, ctop, s);
+    return launch_for<GRMHD_RECON_WENO5, float>(d, t, gam, P, F, ctop, s);
   }
-  return hipGetLastError();
+  if (recon == GRMHD_RECON_MC) return launch_for<GRMHD_RECON_MC, double>(d, t, gam, P, F, ctop, s);
+  return launch_for<GRMHD_RECON_WENO5, double>(d, t, gam, P, F, ctop, s);
 }
 
 hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon, bool mixed, bool corrector,
@@ -177,11 +259,9 @@ hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon
   const dim3 blk(bv.stx, bv.sty, 1), grd(totals[PH_SWEEP]);
   const int c = corrector ? 1 : 0, w = want_ctop ? 1 : 0;
   if (mixed) {
-    if (recon == GRMHD_RECON_MC) hipLaunchKernelGGL((sweep_batch_kernel<GRMHD_RECON_MC, float>), grd, blk, 0, s, bv, c, w);
-    else hipLaunchKernelGGL((sweep_batch_kernel<GRMHD_RECON_WENO5, float>), grd, blk, 0, s, bv, c, w);
-  } else {
-    if (recon == GRMHD_RECON_MC) hipLaunchKernelGGL((sweep_batch_kernel<GRMHD_RECON_MC, double>), grd, blk, 0, s, bv, c, w);
-    else hipLaunchKernelGGL((sweep_batch_kernel<GRMHD_RECON_WENO5, double>), grd, blk, 0, s, bv, c, w);
+    if (recon == GRMHD_RECON_MC) return launch_batch_for<GRMHD_RECON_MC, float>(bv, grd, blk, c, w, s);
+    return launch_batch_for<GRMHD_RECON_WENO5, float>(bv, grd, blk, c, w, s);
   }
-  return hipGetLastError();
+  if (recon == GRMHD_RECON_MC) return launch_batch_for<GRMHD_RECON_MC, double>(bv, grd, blk, c, w, s);
+  return launch_batch_for<GRMHD_RECON_WENO5, double>(bv, grd, blk, c, w, s);
 }

@@ -34,7 +34,7 @@ from . import _binding as B
 WIDTHS = (32, 64, 128, 256)
 ROWS = (1, 2, 4, 8, 16)
 MAX_THREADS = {"sweep": 512, "update": 256}   # the kernels' launch bounds
-DEFAULT = {"sweep": (128, 4), "update": (64, 4)}
+DEFAULT = {"sweep": (64, 8), "update": (64, 4)}
 
 SWEEP_CLASSES = ("sweeps",)
 UPDATE_CLASSES = ("update", "fixup")

@@ -45,7 +45,7 @@ def test_any_tile_gives_the_same_bits(lib, make):
 def test_tile_validation(lib):
     prm, _ = problems.linear_modes(n=8)
     sim = lib.Sim(prm)
-    assert sim.get_tiles("sweep") == (128, 4)
+    assert sim.get_tiles("sweep") == (64, 8)
     assert sim.get_tiles("update") == (64, 4)
     for bad in [(48, 4), (32, 3), (512, 1), (8, 8), (16, 3), (0, 4), (64, 0), (64, 16)]:
         with pytest.raises(lib.GrmhdError):
