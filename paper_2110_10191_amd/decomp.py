@@ -27,6 +27,7 @@ from ._binding import (Sim, grmhd_fill_ghosts, grmhd_update, grmhd_fixup, grmhd_
 HALO_X3 = (1 << 4) | (1 << 5)          # both x3 sides of a part hold neighbour zones
 
 BC_PERIODIC, BC_DIRICHLET = 0, 3
+KERR_CKS = 3
 
 
 class SlabSplit:
@@ -36,6 +37,11 @@ class SlabSplit:
             raise ValueError("n3 must be a multiple of the number of parts")
         if list(prm["bc"][2]) != [BC_PERIODIC, BC_PERIODIC]:
             raise ValueError("the split needs a periodic x3 direction")
+        if prm["coords"] == KERR_CKS:
+            # each part builds its own tables from its own x3 extent; where the
+            # geometry depends on x3 those would match the whole domain's only
+            # to rounding, and the centred-difference connection magnifies that
+            raise ValueError("the split needs geometry that does not depend on x3")
         m = n3 // parts
         if m < NG:
             raise ValueError(f"each part needs at least {NG} x3 planes")
