@@ -31,8 +31,11 @@ def evolve(lib, prm, P0, nsteps, sweep=None, update=None):
 @pytest.mark.parametrize("make", [
     lambda: problems.fm_torus(n1=72, n2=20, n3=5),
     lambda: problems.fm_torus(n1=40, n2=18, n3=3, recon=problems.RECON_WENO5, precision=problems.MIXED),
+    # FP64 WENO5 stages the widest LDS tiles: 128 x 4 and 256 x 1 need more
+    # than the default 64 KiB a block (76.6 and 100 KB)
+    lambda: problems.fm_torus(n1=40, n2=18, n3=3, recon=problems.RECON_WENO5),
     lambda: problems.bondi(n1=37, n2=13, n3=2, a=0.5),
-], ids=["torus_mc_fp64", "torus_weno5_mixed", "bondi"])
+], ids=["torus_mc_fp64", "torus_weno5_mixed", "torus_weno5_fp64", "bondi"])
 def test_any_tile_gives_the_same_bits(lib, make):
     prm, P0 = make()
     ref, dt_ref = evolve(lib, prm, P0, 3)
