@@ -224,15 +224,25 @@ def serving_record(n_jobs=48, lam=7.0, seed=4, steps=(100, 400), identity=2):
 
     rng = np.random.default_rng(seed + 1000)
     sample = sorted(int(x) for x in rng.choice(len(specs), size=identity, replace=False))
-    eng = serve.GpuEngine(recon, precision)
+    # batch tiles from the autotuner, timed on the stream's largest grid
+    from paper_2110_10191_amd import tune
+    t_tune = time.perf_counter()
+    prm_big, P_big = make_state(max(specs, key=lambda sp: sp.zones))
+    import tempfile
+    with tempfile.TemporaryDirectory() as tmp:
+        tiles = tune.tune_problem(prm_big, P_big, cache=tune.TileCache(path=os.path.join(tmp, "tiles.json")),
+                                  force=True, steps=2, repeats=2)
+    t_tune = time.perf_counter() - t_tune
+    eng = serve.GpuEngine(recon, precision, tiles=tiles)
     srv = serve.Server(eng, make_state, int(200e9), quantum=25, keep=sample)
     rep = srv.run(specs)
     summ = rep.summary()
-    ident = serve.identity_check(rep, specs, make_state, recon, precision, sample)
+    ident = serve.identity_check(rep, specs, make_state, recon, precision, sample, tiles=tiles)
     summ["identity_alone_vs_mix"] = {str(k): v for k, v in ident.items()}
     summ["config"] = {"workload": f"poisson stream of {n_jobs} torus / Kerr Bondi jobs (64-192 x 64-128 x 32-64)",
                       "lam_per_s": lam, "seed": seed, "steps": list(steps), "recon": "weno5",
-                      "precision": "mixed", "budget_gb": 200.0, "quantum": 25}
+                      "precision": "mixed", "budget_gb": 200.0, "quantum": 25,
+                      "tiles": {k: list(v) for k, v in tiles.items()}, "tune_s": t_tune}
     return summ
 
 
