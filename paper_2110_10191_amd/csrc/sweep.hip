@@ -25,11 +25,6 @@
 
 namespace {
 
-// the face of direction D at the lower D-face of cell (k, j, i): store the
-// flux (all but the face-normal field component, which Flux-CT replaces by
-// zero and nothing reads) and return the signal speed for the Courant maximum
-// (0 for a face with a transverse ghost index, +inf when its speeds are not
-// finite)
 // the block's x3 plane of primitives with the stencil halo in x1 and x2,
 // [8][lh][lw] of T, cells (ib + li, jb + lj)
 template <typename T>
@@ -46,6 +41,11 @@ constexpr int halo_lo() { return RECON == GRMHD_RECON_MC ? 2 : 3; }
 template <int RECON>
 constexpr int halo_hi() { return RECON == GRMHD_RECON_MC ? 1 : 2; }
 
+// the face of direction D at the lower D-face of cell (k, j, i): store the
+// flux (all but the face-normal field component, which Flux-CT replaces by
+// zero and nothing reads) and return the signal speed for the Courant maximum
+// (0 for a face with a transverse ghost index, +inf when its speeds are not
+// finite)
 template <int D, int RECON, typename T>
 __device__ inline double one_face(const Dims& d, const double* __restrict__ P, const PlaneTile<T>& pt,
                                   const T* __restrict__ tab, T* __restrict__ F, T gam, int i, int j, int k) {
