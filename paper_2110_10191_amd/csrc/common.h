@@ -328,6 +328,30 @@ __device__ inline void block_max_to(double v, unsigned long long* dst) {
   }
 }
 
+// block_max_to for three values at once into dst[0..2]: one barrier, and
+// the atomic only where the block's maximum exceeds the running one (values
+// only grow, so a stale read can only cost an unneeded atomic)
+__device__ inline void block_max3_to(double a, double b, double c, unsigned long long* dst) {
+  __shared__ double part3[3][16];
+  const int tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+  const int nthr = blockDim.x * blockDim.y * blockDim.z;
+  a = wave_max(a + 0.0);
+  b = wave_max(b + 0.0);
+  c = wave_max(c + 0.0);
+  if ((tid & 63) == 0) {
+    part3[0][tid >> 6] = a;
+    part3[1][tid >> 6] = b;
+    part3[2][tid >> 6] = c;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double m = part3[tid][0];
+    for (int w = 1; w < (nthr + 63) / 64; ++w) m = fmax(m, part3[tid][w]);
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(m + 0.0);
+    if (__hip_atomic_load(dst + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < bits) atomicMax(dst + tid, bits);
+  }
+}
+
 // block sum of v, then one atomic add into dst (and into dst2 when given)
 __device__ inline void block_count_to(int v, unsigned int* dst, unsigned int* dst2 = nullptr) {
   __shared__ int cpart[16];

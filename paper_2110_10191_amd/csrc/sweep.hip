@@ -152,14 +152,7 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
   if (ok && i >= 0) c1 = one_face<1, RECON, T>(d, P, pt, t1, F1, gam, i, j, k);
   if (ok && j >= 0) c2 = one_face<2, RECON, T>(d, P, pt, t2, F2, gam, i, j, k);
   if (ok && k >= 0) c3 = one_face<3, RECON, T>(d, P, pt, t3, F3, gam, i, j, k);
-  if (ctop) {
-    // three block reductions through the same shared scratch, one after another
-    block_max_to(c1, ctop + 0);
-    __syncthreads();
-    block_max_to(c2, ctop + 1);
-    __syncthreads();
-    block_max_to(c3, ctop + 2);
-  }
+  if (ctop) block_max3_to(c1, c2, c3, ctop);
 }
 
 template <int RECON, typename T>
