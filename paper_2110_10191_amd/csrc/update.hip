@@ -355,10 +355,14 @@ __device__ void fixup_body(const Dims& d, const double* __restrict__ cent, const
   if (!fin) atomicAdd(&ctr->bad, 1u);
 }
 
+// a grid of at most FIXUP_BLOCKS blocks strides over the tiles: when no zone
+// failed (almost always) every block exits after one read of the counter
+constexpr unsigned FIXUP_BLOCKS = 2048;  // a multiple of the XCD count
 __global__ __launch_bounds__(256) void fixup_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
                                                     double* P, const int8_t* __restrict__ flags, Counters* ctr,
-                                                    int halo) {
-  fixup_body(d, cent, up, P, flags, ctr, halo, (int)blockIdx.x);
+                                                    int halo, int ntiles) {
+  if (ctr->fail == 0u) return;
+  for (int b = (int)blockIdx.x; b < ntiles; b += (int)gridDim.x) fixup_body(d, cent, up, P, flags, ctr, halo, b);
 }
 
 __global__ __launch_bounds__(256) void fixup_batch_kernel(BatchView bv, int corrector) {
@@ -442,8 +446,10 @@ hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const Updat
 
 hipError_t launch_fixup(const Dims& d, const Tables& t, const UpdateParams& up, double* P, const int8_t* flags,
                         Counters* ctr, int halo, hipStream_t s) {
-  const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
-  hipLaunchKernelGGL(fixup_kernel, dim3(nblk), dim3(d.utx, d.uty, 1), 0, s, d, t.cent, up, P, flags, ctr, halo);
+  const unsigned ntiles = xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
+  const unsigned nblk = ntiles < FIXUP_BLOCKS ? ntiles : FIXUP_BLOCKS;
+  hipLaunchKernelGGL(fixup_kernel, dim3(nblk), dim3(d.utx, d.uty, 1), 0, s, d, t.cent, up, P, flags, ctr, halo,
+                     (int)ntiles);
   return hipGetLastError();
 }
 
