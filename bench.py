@@ -97,6 +97,25 @@ def split_design_bytes(kernel, prm, mixed):
     raise KeyError(kernel)
 
 
+def arithmetic_ceiling(flops_per_step, zones, per_zc, step_s):
+    """The step's counted VALU work against its compulsory bytes.
+
+    A step that does flops_per_step FP64 operations cannot take less than
+    flops_per_step / FP64_PEAK seconds, so the compulsory bytes it moves
+    (per_zc per zone) can reach at most this fraction of the HBM peak:
+    (zones * per_zc / (flops_per_step / FP64_PEAK)) / HBM_PEAK, capped at 1.
+    Where the method's FP64 operations per compulsory byte exceed the chip's
+    balance (FP64_PEAK / HBM_PEAK, 9.8 flop/B) the step is bound by FP64
+    issue, not by HBM, and the HBM fraction has that ceiling."""
+    bytes_step = zones * per_zc
+    t_min = flops_per_step / FP64_PEAK
+    return {"fp64_flops_per_zone_cycle": flops_per_step / zones,
+            "flop_per_compulsory_byte": flops_per_step / bytes_step,
+            "machine_balance_flop_per_byte": FP64_PEAK / HBM_PEAK,
+            "step_compulsory_frac_ceiling": min(1.0, bytes_step / t_min / HBM_PEAK) if t_min > 0 else 1.0,
+            "step_fp64_frac": flops_per_step / step_s / FP64_PEAK}
+
+
 def device_copy_bandwidth(torch, dev, gib=1.0, reps=5):
     """Best of a few plain device-to-device copies, bytes read + written per second."""
     nel = int(gib * 2 ** 30) // 8
@@ -526,6 +545,11 @@ def main():
                 valu[k] = {"fp64_TFLOPs": rec["fp64"] / t / 1e12, "fp64_frac": rec["fp64"] / t / FP64_PEAK,
                            "fp32_TFLOPs": rec["fp32"] / t / 1e12, "fp32_frac": rec["fp32"] / t / FP32_PEAK}
         views["valu"] = valu
+        if all(k in flops and kernels.get(k, (0, 0))[1] for k in ("sweeps", "update")):
+            # FP64 work of a step: the two hot kernels' counted flops per launch
+            # times their launches per step (the ghosts, fixup and dt are bytes)
+            per_step = sum(flops[k]["fp64"] * kernels[k][1] / args.steps for k in ("sweeps", "update"))
+            views["arithmetic_ceiling"] = arithmetic_ceiling(per_step, zones, per_zc, secs / args.steps)
     roofline["views"] = views
 
     if args.electrons:

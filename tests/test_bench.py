@@ -63,3 +63,20 @@ def test_more_than_one_gpu_is_refused_with_a_message():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_arithmetic_ceiling_of_the_hbm_fraction():
+    zones, per_zc = 1000, 320.0
+    balance = bench.FP64_PEAK / bench.HBM_PEAK
+    # exactly the machine balance: a step at the FP64 peak moves its bytes at the HBM peak
+    at_balance = bench.arithmetic_ceiling(balance * zones * per_zc, zones, per_zc, 1.0)
+    assert abs(at_balance["step_compulsory_frac_ceiling"] - 1.0) < 1e-12
+    # twice the balance: half the HBM peak at best
+    twice = bench.arithmetic_ceiling(2 * balance * zones * per_zc, zones, per_zc, 1.0)
+    assert abs(twice["step_compulsory_frac_ceiling"] - 0.5) < 1e-12
+    assert abs(twice["flop_per_compulsory_byte"] - 2 * balance) < 1e-9
+    # less work than the balance: HBM bound, the ceiling stays 1
+    assert bench.arithmetic_ceiling(0.1 * zones * per_zc, zones, per_zc, 1.0)["step_compulsory_frac_ceiling"] == 1.0
+    # the measured FP64 fraction: flops over the step time against the vector peak
+    r = bench.arithmetic_ceiling(bench.FP64_PEAK * 1e-3, zones, per_zc, 4e-3)
+    assert abs(r["step_fp64_frac"] - 0.25) < 1e-12
