@@ -84,7 +84,7 @@ enum { GRMHD_OPT_FLOORS = 1, GRMHD_OPT_FIXUP = 2 };
  *              r^4 - (x^2 + y^2 + z^2 - a^2) r^2 - a^2 z^2 = 0 (Implementation Notes:
  *              a change of coordinates or background spacetime). The metric
  *              depends on all three coordinates: the geometry tables are 3D
- *              (about 1.4 KB of device memory per zone, counted by
+ *              (about 1.3 KB of device memory per zone, counted by
  *              grmhd_context_bytes; at most 2^25 zones, ghosts and x1
  *              padding included). Boundaries PERIODIC or DIRICHLET only; the
  *              box, ghosts included, must lie outside the unit sphere

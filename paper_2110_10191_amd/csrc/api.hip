@@ -130,10 +130,7 @@ Dims make_dims(const grmhd_problem& p) {
 }
 
 void free_all(grmhd_ctx* c) {
-  // 2D tables alias the x3-face tables to the centre ones
-  void* f3 = c->t.f3 != c->t.cent ? (void*)c->t.f3 : nullptr;
-  void* f3f = c->t.f3f != c->t.centf ? (void*)c->t.f3f : nullptr;
-  void* ptrs[] = {c->t.cent, c->t.f1, c->t.f2, f3, c->t.centf, c->t.f1f, c->t.f2f, f3f,
+  void* ptrs[] = {c->t.cent, c->t.f1, c->t.f2, c->t.f3, c->t.f1f, c->t.f2f, c->t.f3f,
                   c->Ph, c->F[0], c->F[1], c->F[2], c->flags, c->ctr, c->Eh, c->Uk};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -346,8 +343,7 @@ int grmhd_context_bytes(const grmhd_problem* p, int64_t* ctx_bytes, int64_t* sta
   const Dims d = make_dims(*p);
   const size_t ts = (size_t)d.ts, sv = (size_t)d.sv;
   const size_t fsz = p->precision == GRMHD_MIXED ? sizeof(float) : sizeof(double);
-  const int nface = d.tk ? 3 : 2;  // x3-face tables of their own (3D tables only)
-  const size_t tables = (N_CENT + nface * N_FACE) * ts * sizeof(double) + (1 + nface) * N_FACE * ts * sizeof(float);
+  const size_t tables = (N_CENT + 3 * N_FACE) * ts * sizeof(double) + 3 * N_FACE * ts * sizeof(float);
   const size_t scratch = NV * sv * sizeof(double) + 3 * NV * sv * fsz + sv + sizeof(Counters);
   *ctx_bytes = (int64_t)(tables + scratch);
   *state_bytes = (int64_t)(NV * sv * sizeof(double));
@@ -404,11 +400,10 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
   bool ok = dalloc(&c->t.cent, N_CENT * ts * sizeof(double)) == hipSuccess &&
             dalloc(&c->t.f1, N_FACE * ts * sizeof(double)) == hipSuccess &&
             dalloc(&c->t.f2, N_FACE * ts * sizeof(double)) == hipSuccess &&
-            dalloc(&c->t.centf, N_FACE * ts * sizeof(float)) == hipSuccess &&
+            dalloc(&c->t.f3, N_FACE * ts * sizeof(double)) == hipSuccess &&
             dalloc(&c->t.f1f, N_FACE * ts * sizeof(float)) == hipSuccess &&
             dalloc(&c->t.f2f, N_FACE * ts * sizeof(float)) == hipSuccess &&
-            (!c->d.tk || (dalloc(&c->t.f3, N_FACE * ts * sizeof(double)) == hipSuccess &&
-                          dalloc(&c->t.f3f, N_FACE * ts * sizeof(float)) == hipSuccess)) &&
+            dalloc(&c->t.f3f, N_FACE * ts * sizeof(float)) == hipSuccess &&
             dalloc(&c->Ph, NV * sv * sizeof(double)) == hipSuccess &&
             dalloc(&c->F[0], NV * sv * fsz) == hipSuccess && dalloc(&c->F[1], NV * sv * fsz) == hipSuccess &&
             dalloc(&c->F[2], NV * sv * fsz) == hipSuccess && dalloc(&c->flags, sv) == hipSuccess &&
@@ -418,10 +413,6 @@ int grmhd_init(const grmhd_problem* p, void* hip_stream, grmhd_ctx** out) {
     free_all(c);
     delete c;
     return fail(nullptr, GRMHD_ENOMEM, "device allocation failed");
-  }
-  if (!c->d.tk) {
-    c->t.f3 = c->t.cent;
-    c->t.f3f = c->t.centf;
   }
   // one-time clears (outside any captured work); padding stays finite
   hipError_t e = hipMemsetAsync(c->t.cent, 0, N_CENT * ts * sizeof(double), c->stream);

@@ -68,6 +68,28 @@ template <typename S>
 __device__ inline S ldu(const S* base, unsigned byte_off) {
   return *(const S*)((const char*)base + byte_off);
 }
+// The face tables hold their components in pairs: component c of point off
+// at (c & ~1) * ts + 2 * off + (c & 1), so one 16-byte (FP64) or 8-byte
+// (FP32) load per lane brings two components. The centre table keeps one
+// plane per component (c * ts + off).
+__host__ __device__ inline size_t pair_index(int c, size_t ts, size_t off) {
+  return (size_t)(c & ~1) * ts + 2 * off + (size_t)(c & 1);
+}
+template <typename S>
+__host__ __device__ inline const S* face_plane(const S* tab, const Dims& d, int k) {
+  return tab + 2 * (size_t)(k + NG) * (size_t)d.tk;
+}
+template <typename S>
+struct pair_of;
+template <>
+struct pair_of<double> {
+  using type = double2;
+};
+template <>
+struct pair_of<float> {
+  using type = float2;
+};
+
 template <typename T>
 struct Geo {
   T gcov[10];
@@ -76,7 +98,7 @@ struct Geo {
   T alpha;
 };
 
-// component c of a table lives at tab + c * ts; off is the point index (tab_of)
+// centre table: component c lives at tab + c * ts; off is the point index (tab_of)
 template <typename T, typename S>
 __device__ inline void load_geo(Geo<T>& g, const S* __restrict__ tab, int ts, int off) {
   const unsigned bo = (unsigned)off * (unsigned)sizeof(S);
@@ -86,6 +108,30 @@ __device__ inline void load_geo(Geo<T>& g, const S* __restrict__ tab, int ts, in
   for (int c = 0; c < 10; ++c) g.gcon[c] = (T)ldu(tab + (size_t)(T_GCON + c) * ts, bo);
   g.gdet = (T)ldu(tab + (size_t)T_GDET * ts, bo);
   g.alpha = (T)ldu(tab + (size_t)T_ALPHA * ts, bo);
+}
+
+// the same from a face table (paired components; off as above, tab the plane
+// from face_plane)
+template <typename T, typename S>
+__device__ inline void load_face_geo(Geo<T>& g, const S* __restrict__ tab, int ts, int off) {
+  using P2 = typename pair_of<S>::type;
+  const unsigned bo = (unsigned)off * (unsigned)(2 * sizeof(S));
+  auto ld = [&](int c0) -> P2 { return *(const P2*)((const char*)(tab + (size_t)c0 * ts) + bo); };
+#pragma unroll
+  for (int c = 0; c < 10; c += 2) {
+    const P2 v = ld(T_GCOV + c);
+    g.gcov[c] = (T)v.x;
+    g.gcov[c + 1] = (T)v.y;
+  }
+#pragma unroll
+  for (int c = 0; c < 10; c += 2) {
+    const P2 v = ld(T_GCON + c);
+    g.gcon[c] = (T)v.x;
+    g.gcon[c + 1] = (T)v.y;
+  }
+  const P2 v = ld(T_GDET);
+  g.gdet = (T)v.x;
+  g.alpha = (T)v.y;
 }
 
 // ---------------------------------------------------------------------------
@@ -201,7 +247,8 @@ __device__ inline void signal_speeds(const Fluid<T>& f, const Geo<T>& g, T gam, 
 template <typename T>
 __device__ inline T mc_slope(T pm, T p0, T pp) {
   const T dm = p0 - pm, dp = pp - p0, dc = T(0.5) * (pp - pm);
-  const T mag = fmin(fmin(T(2) * fabs(dm), T(2) * fabs(dp)), fabs(dc));
+  // min(2|dm|, 2|dp|) = 2 min(|dm|, |dp|) exactly
+  const T mag = fmin(T(2) * fmin(fabs(dm), fabs(dp)), fabs(dc));
   return (dm * dp > T(0)) ? copysign(mag, dc) : T(0);
 }
 

@@ -142,26 +142,33 @@ __device__ double invert4(const double m[4][4], double b[4][4]) {
   return det;
 }
 
-// write metric, inverse (upper triangle), sqrt(-g) and lapse of one point
+// write metric, inverse (upper triangle), sqrt(-g) and lapse of one point:
+// into the centre table (dt, one plane per component; ft null) or into a face
+// table and its float copy (paired components)
 __device__ void store_point(double x1, double x2, double x3, const grmhd_problem& p, double* dt, float* ft,
                             size_t ts, int off, double gcon_out[4][4]) {
   double g[4][4], gi[4][4];
   gcov_code(x1, x2, x3, p, g);
   const double det = invert4(g, gi);
+  auto at = [&](int c) -> size_t { return ft ? pair_index(c, ts, (size_t)off) : (size_t)c * ts + (size_t)off; };
   for (int m = 0; m < 4; ++m)
     for (int n = m; n < 4; ++n) {
       const int c = sidx(m, n);
-      dt[(T_GCOV + c) * ts + off] = g[m][n];
-      dt[(T_GCON + c) * ts + off] = gi[m][n];
-      ft[(T_GCOV + c) * ts + off] = (float)g[m][n];
-      ft[(T_GCON + c) * ts + off] = (float)gi[m][n];
+      dt[at(T_GCOV + c)] = g[m][n];
+      dt[at(T_GCON + c)] = gi[m][n];
+      if (ft) {
+        ft[at(T_GCOV + c)] = (float)g[m][n];
+        ft[at(T_GCON + c)] = (float)gi[m][n];
+      }
     }
   const double gdet = sqrt(fabs(det));
   const double alpha = 1.0 / sqrt(-gi[0][0]);
-  dt[T_GDET * ts + off] = gdet;
-  dt[T_ALPHA * ts + off] = alpha;
-  ft[T_GDET * ts + off] = (float)gdet;
-  ft[T_ALPHA * ts + off] = (float)alpha;
+  dt[at(T_GDET)] = gdet;
+  dt[at(T_ALPHA)] = alpha;
+  if (ft) {
+    ft[at(T_GDET)] = (float)gdet;
+    ft[at(T_ALPHA)] = (float)alpha;
+  }
   if (gcon_out)
     for (int m = 0; m < 4; ++m)
       for (int n = 0; n < 4; ++n) gcon_out[m][n] = gi[m][n];
@@ -182,10 +189,12 @@ __global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t) {
   const bool k3 = p.coords == GRMHD_KERR_CKS;
 
   double gcon[4][4];
-  store_point(x1c, x2c, x3c, p, t.cent, t.centf, ts, off, gcon);
+  store_point(x1c, x2c, x3c, p, t.cent, nullptr, ts, off, gcon);
   store_point(x1f, x2c, x3c, p, t.f1, t.f1f, ts, off, nullptr);
   store_point(x1c, x2f, x3c, p, t.f2, t.f2f, ts, off, nullptr);
-  if (k3) store_point(x1c, x2c, x3f, p, t.f3, t.f3f, ts, off, nullptr);
+  // 2D tables: the metric does not depend on x3, and the x3-face table holds
+  // the centre values
+  store_point(x1c, x2c, k3 ? x3f : x3c, p, t.f3, t.f3f, ts, off, nullptr);
 
   // connection: Gamma_kmn = (d_n g_km + d_m g_kn - d_k g_mn)/2, Gamma^l_mn = g^lk Gamma_kmn,
   // derivatives by centred differences in x1, x2 and (3D tables) x3; d_t = 0

@@ -6,16 +6,20 @@
 
 #include "common.h"
 
-// [N_CENT or N_FACE][p2][p1] (2D) or [..][p3][p2][p1] (3D, Dims::tk != 0)
+// Geometry tables over the padded (x1, x2) points (2D) or (x1, x2, x3) points
+// (3D, Dims::tk != 0), ts points a component: the centre table one plane per
+// component, [N_CENT][points]; the face tables two components interleaved
+// per point, [N_FACE / 2][points][2] (pair_index), so the face-flux pass
+// loads them two at a time. 2D tables hold the x3-face table too (the centre
+// values, the metric not depending on x3).
 struct Tables {
-  double* cent;   // centre tables
-  double* f1;     // x1-, x2-, x3-face tables (f3 is cent for 2D tables)
+  double* cent;   // centre table, N_CENT components
+  double* f1;     // x1-, x2-, x3-face tables, N_FACE components in pairs
   double* f2;
   double* f3;
-  float* centf;   // float copies of the first N_FACE components (mixed precision)
-  float* f1f;
+  float* f1f;     // float copies of the face tables (mixed precision)
   float* f2f;
-  float* f3f;     // centf for 2D tables
+  float* f3f;
 };
 
 // device counters kept by a context

@@ -14,7 +14,7 @@
 // HBM once for the three directions and one launch replaces three. A block
 // first copies its tile of the x3 plane, with the reconstruction halo in x1
 // and x2, into LDS (coalesced along x1); the x1 and x2 stencils then come
-// from LDS and only the x3 stencil from the state. The
+// from LDS and only the other planes of the x3 stencil from the state. The
 // per-direction maximum of ctop over the faces with interior transverse index
 // feeds the Courant step (one atomic max per block and direction); a face with
 // a NaN speed counts as +inf there, which the step reports as a non-finite
@@ -57,7 +57,8 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
     const T* ql = pt.lds + v * pt.plane + pt.lj * pt.lw + pt.li;
     const double* qg = P + v * d.sv + c;
     const int st = (D == 1) ? 1 : pt.lw;
-    auto at = [&](int o) -> T { return D == 3 ? (T)qg[o * d.s3] : ql[o * st]; };
+    // the cell's own value from the LDS tile in every direction
+    auto at = [&](int o) -> T { return (D == 3 && o != 0) ? (T)qg[o * d.s3] : ql[o * st]; };
     if (RECON == GRMHD_RECON_MC) {
       const T a = at(-2), bb = at(-1), e = at(0), f = at(1);
       PL[v] = bb + T(0.5) * mc_slope(a, bb, e);
@@ -69,7 +70,7 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
     }
   }
   Geo<T> g;
-  load_geo(g, tab_plane(tab, d, k), d.ts, tab_of(d, j, i));
+  load_face_geo(g, face_plane(tab, d, k), d.ts, tab_of(d, j, i));
   T FL[NV], UL[NV], cpL, cmL;
   {
     Fluid<T> f;

@@ -152,7 +152,8 @@ def test_context_bytes_without_a_device(lib):
     n1p = -(-(64 + 6) // 8) * 8
     cells = (16 + 6) * (32 + 6) * n1p
     assert sb == 8 * 8 * cells
-    tables = (64 + 2 * 22) * 8 * (32 + 6) * n1p + 3 * 22 * 4 * (32 + 6) * n1p
+    # centre table, three face tables (the x3 one with the centre values) and their float copies
+    tables = (64 + 3 * 22) * 8 * (32 + 6) * n1p + 3 * 22 * 4 * (32 + 6) * n1p
     assert cb > tables + sb + 3 * sb                    # half-step state + three fp64 flux arrays
     prm_m = dict(prm, precision=problems.MIXED)
     cbm, sbm = lib.grmhd_context_bytes(prm_m)
@@ -168,7 +169,7 @@ def test_cartesian_kerr_schild_tables_are_3d(lib):
     n1p = -(-(24 + 6) // 8) * 8
     cells = (16 + 6) * (20 + 6) * n1p
     assert sb == 8 * 8 * cells
-    tables = (64 + 3 * 22) * 8 * cells + 4 * 22 * 4 * cells      # 3D, with x3-face tables
+    tables = (64 + 3 * 22) * 8 * cells + 3 * 22 * 4 * cells      # 3D, with x3-face tables
     scratch = 8 * 8 * cells + 3 * 8 * 8 * cells + cells       # half-step state, fluxes, flags
     assert tables + scratch <= cb <= tables + scratch + 4096
 
