@@ -163,15 +163,19 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
             const ElectronPass* el = nullptr, int8_t* flags = nullptr, bool fix = true) {
   int8_t* fl = flags ? flags : c->flags;
   hipStream_t s = c->stream;
+  // the counters the face fluxes and the update count into start at zero (the
+  // ghost fill clears them when there is one)
+  const int reset_mask = want_ctop ? (1 | 4) : 4;
   if (fill) {
     ProfScope ps(c->prof, s, GRMHD_K_GHOSTS);
-    HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s), "ghost fill");
+    HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s, c->ctr, reset_mask), "ghost fill");
+  } else {
+    HIP_OR_FAIL(c, launch_reset(c->ctr, reset_mask, s), "reset");
   }
   if (el) {
     ProfScope ps(c->prof, s, GRMHD_K_ELECTRONS);
     HIP_OR_FAIL(c, launch_fill_scalar_ghosts(c->p, c->d, el->Es, el->Eb, s), "scalar ghost fill");
   }
-  HIP_OR_FAIL(c, launch_reset(c->ctr, want_ctop ? (1 | 4) : 4, s), "reset");
   {
     ProfScope ps(c->prof, s, GRMHD_K_SWEEPS);
     HIP_OR_FAIL(c, launch_sweeps(c->p.recon, c->mixed, c->d, c->t, c->p.gam, Ps, c->F, want_ctop ? c->ctr->ctop : nullptr,

@@ -1,8 +1,10 @@
 // Ghost zones, the div B monitor, counter resets and the per-job time step.
 //
-// Ghost fill (three ghost layers), in the order x1 (interior j, k), x2 (all i,
-// interior k), x3 (all i, j) so corners are consistent (the electron-heating
-// scalars follow the same rules without the inflow fix and the axis sign change):
+// Ghost fill (three ghost layers): the result of filling in the order x1
+// (interior j, k), x2 (all i, interior k), x3 (all i, j), so corners are
+// consistent, computed in one launch with each ghost taken straight from the
+// interior zone it comes from (the electron-heating scalars follow the same
+// rules without the inflow fix and the axis sign change):
 //   periodic  - wrap;
 //   outflow   - copy the nearest interior zone; where the copied radial
 //               four-velocity points into the domain, u~1 is reset so u^1 = 0;
@@ -15,7 +17,8 @@
 
 namespace {
 
-constexpr int GB = 64;           // threads per block of the x2 / x3 ghost fills
+__device__ void reset_counters(Counters* c, int mask);
+
 constexpr int MAX_DEVICES = 64;  // devices the no-allocation scratch lookup keeps
 
 __device__ inline int wrap(int x, int n) {
@@ -26,11 +29,11 @@ __device__ inline int wrap(int x, int n) {
 // where an outflow ghost's u^1 points into the domain, set u~1 = c Gamma with
 // c = alpha g^{t1}, Gamma the positive root of
 // (1 - g11 c^2) G^2 - 2 c (g12 v2 + g13 v3) G - (1 + g_jk v^j v^k) = 0
-__device__ void inflow_fix(double* P, int stride, int c0, const double* cent, int ts, int toff,
-                           int side) {
+// (q: the ghost's primitives)
+__device__ void inflow_fix(double* q, const double* cent, int ts, int toff, int side) {
   Geo<double> g;
   load_geo(g, cent, ts, toff);
-  const double v1 = P[2 * stride + c0], v2 = P[3 * stride + c0], v3 = P[4 * stride + c0];
+  const double v1 = q[2], v2 = q[3], v3 = q[4];
   const double lor = sqrt(lorentz_sq(g.gcov, v1, v2, v3));
   const double u1 = v1 - lor * g.alpha * g.gcon[1];
   const bool bad = side == 0 ? (u1 > 0.0) : (u1 < 0.0);
@@ -41,139 +44,149 @@ __device__ void inflow_fix(double* P, int stride, int c0, const double* cent, in
   const double G = g.gcov[5] * v2 + g.gcov[6] * v3;
   const double H = g.gcov[7] * v2 * v2 + 2.0 * g.gcov[8] * v2 * v3 + g.gcov[9] * v3 * v3;
   const double root = (c * G + sqrt(c * c * G * G + qa * (1.0 + H))) / qa;
-  P[2 * stride + c0] = c * root;
+  q[2] = c * root;
 }
 
-// ---- bodies: idx / b are thread / block indices within one job's grid.
-// NVAR variables of stride d.sv; SCALAR: advected scalars (no inflow fix, no
-// sign change on the axis), otherwise the primitives.
+// ---- bodies: idx is the thread index within one job's grid. NVAR variables of
+// stride d.sv; SCALAR: advected scalars (no inflow fix, no sign change on the
+// axis), otherwise the primitives.
 
-template <int NVAR = NV, bool SCALAR = false>
-__device__ void ghost_x1_body(const grmhd_problem& p, const Dims& d, const double* cent, double* P,
-                              const double* dsrc, int idx) {
-  if (idx >= 2 * NG * d.n2 * d.n3) return;
-  const int t = idx % (2 * NG);
-  const int rest = idx / (2 * NG);
-  const int j = rest % d.n2;
-  const int k = rest / d.n2;
-  const int side = t / NG, m = t % NG;
-  const int g = side == 0 ? -1 - m : d.n1 + m;
-  const int type = p.bc[0][side];
-  const int cg = cell_of(d, k, j, g);
-  if (type == GRMHD_BC_DIRICHLET) {
-    if (dsrc != P)
-      for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
-    return;
+// The value the fill in the order x1 (interior j, k), x2 (all i, interior k),
+// x3 (all i, j) leaves in ghost cell (i, j, k), taken straight from the
+// interior cell (or the Dirichlet source) it comes from: the x3 rule maps k to
+// an interior plane, the x2 rule j to an interior row, the x1 rule i to an
+// interior column, and the value changes on the way back in the fill's order
+// (inflow fix at the x1 ghost, sign change across the axis). No cell is read
+// that the same launch writes, so one launch does all three directions.
+template <int NVAR, bool SCALAR>
+__device__ void ghost_cell(const grmhd_problem& p, const Dims& d, const double* cent, double* P,
+                           const double* dsrc, int i, int j, int k) {
+  const int cg = cell_of(d, k, j, i);
+  int sk = k, sj = j, si = i;
+  if (k < 0 || k >= d.n3) {
+    const int side = k < 0 ? 0 : 1, type = p.bc[2][side];
+    if (type == GRMHD_BC_DIRICHLET) {
+      if (dsrc != P)
+        for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+      return;
+    }
+    sk = type == GRMHD_BC_PERIODIC ? wrap(k, d.n3) : (side == 0 ? 0 : d.n3 - 1);
   }
-  const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n1) : (side == 0 ? 0 : d.n1 - 1);
-  const int cs = cell_of(d, k, j, src);
-  for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
-  if (!SCALAR && type == GRMHD_BC_OUTFLOW) inflow_fix(P, d.sv, cg, tab_plane(cent, d, k), d.ts, tab_of(d, j, g), side);
+  bool flip = false;
+  if (j < 0 || j >= d.n2) {
+    const int side = j < 0 ? 0 : 1, type = p.bc[1][side];
+    if (type == GRMHD_BC_DIRICHLET) {
+      // the x2 fill leaves the source's value at (i, j, sk)
+      const int cs = cell_of(d, sk, j, i);
+      if (dsrc != P || cs != cg)
+        for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cs];
+      return;
+    }
+    const int m = side == 0 ? -1 - j : j - d.n2;
+    if (type == GRMHD_BC_PERIODIC) sj = wrap(j, d.n2);
+    else if (type == GRMHD_BC_POLAR) sj = side == 0 ? m : d.n2 - 1 - m;
+    else sj = side == 0 ? 0 : d.n2 - 1;
+    flip = !SCALAR && type == GRMHD_BC_POLAR;
+  }
+  const double* from = P;
+  int fix_side = -1;
+  if (i < 0 || i >= d.n1) {
+    const int side = i < 0 ? 0 : 1, type = p.bc[0][side];
+    if (type == GRMHD_BC_DIRICHLET) {
+      from = dsrc;  // the x1 fill leaves the source's value at (i, sj, sk)
+    } else {
+      si = type == GRMHD_BC_PERIODIC ? wrap(i, d.n1) : (side == 0 ? 0 : d.n1 - 1);
+      if (!SCALAR && type == GRMHD_BC_OUTFLOW) fix_side = side;
+    }
+  }
+  const int cs = cell_of(d, sk, sj, si);
+  if (from == P && cs == cg) return;  // a Dirichlet ghost that keeps its value
+  double q[NVAR];
+  for (int v = 0; v < NVAR; ++v) q[v] = from[v * d.sv + cs];
+  if constexpr (!SCALAR) {
+    if (fix_side >= 0) inflow_fix(q, tab_plane(cent, d, sk), d.ts, tab_of(d, sj, i), fix_side);
+    if (flip) {
+      q[3] = -q[3];
+      q[6] = -q[6];
+    }
+  }
+  for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = q[v];
 }
 
-__device__ inline int ghost_tiles(const Dims& d) { return (d.n1 + 2 * NG + GB - 1) / GB; }
-
-template <int NVAR = NV, bool SCALAR = false>
-__device__ void ghost_x2_body(const grmhd_problem& p, const Dims& d, double* P, const double* dsrc, int b) {
-  const int tiles = ghost_tiles(d);
-  const int bx = b % tiles, rest = b / tiles;
-  const int t = rest % (2 * NG), k = rest / (2 * NG);
-  const int i = bx * GB + (int)threadIdx.x - NG;
-  if (i >= d.n1 + NG) return;
-  const int side = t / NG, m = t % NG;
-  const int g = side == 0 ? -1 - m : d.n2 + m;
-  const int type = p.bc[1][side];
-  const int cg = cell_of(d, k, g, i);
-  if (type == GRMHD_BC_DIRICHLET) {
-    if (dsrc != P)
-      for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
-    return;
-  }
-  int src;
-  if (type == GRMHD_BC_PERIODIC) src = wrap(g, d.n2);
-  else if (type == GRMHD_BC_POLAR) src = side == 0 ? m : d.n2 - 1 - m;
-  else src = side == 0 ? 0 : d.n2 - 1;
-  const int cs = cell_of(d, k, src, i);
-  for (int v = 0; v < NVAR; ++v) {
-    const double q = P[v * d.sv + cs];
-    P[v * d.sv + cg] = (!SCALAR && type == GRMHD_BC_POLAR && (v == 3 || v == 6)) ? -q : q;
-  }
+// thread idx of the fused fill: the x1 ghosts at interior (j, k) (the six of a
+// row side by side), then the x2 ghosts at every i and interior k, then the x3
+// ghosts at every (i, j), i fastest
+__host__ __device__ inline int ghost_threads(const Dims& d) {
+  const int w = d.n1 + 2 * NG, h = d.n2 + 2 * NG;
+  return 2 * NG * (d.n2 * d.n3 + w * d.n3 + w * h);
 }
 
 template <int NVAR = NV, bool SCALAR = false>
-__device__ void ghost_x3_body(const grmhd_problem& p, const Dims& d, double* P, const double* dsrc, int b) {
-  const int tiles = ghost_tiles(d);
-  const int bx = b % tiles, rest = b / tiles;
-  const int j = rest % (d.n2 + 2 * NG) - NG, t = rest / (d.n2 + 2 * NG);
-  const int i = bx * GB + (int)threadIdx.x - NG;
-  if (i >= d.n1 + NG) return;
-  const int side = t / NG, m = t % NG;
-  const int g = side == 0 ? -1 - m : d.n3 + m;
-  const int type = p.bc[2][side];
-  const int cg = cell_of(d, g, j, i);
-  if (type == GRMHD_BC_DIRICHLET) {
-    if (dsrc != P)
-      for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = dsrc[v * d.sv + cg];
+__device__ void ghost_fill_body(const grmhd_problem& p, const Dims& d, const double* cent, double* P,
+                                const double* dsrc, int idx) {
+  const int w = d.n1 + 2 * NG, h = d.n2 + 2 * NG;
+  const int t1 = 2 * NG * d.n2 * d.n3, t2 = 2 * NG * w * d.n3, t3 = 2 * NG * w * h;
+  int i, j, k;
+  if (idx < t1) {
+    const int t = idx % (2 * NG), rest = idx / (2 * NG);
+    j = rest % d.n2;
+    k = rest / d.n2;
+    i = t < NG ? -1 - t : d.n1 + (t - NG);
+  } else if ((idx -= t1) < t2) {
+    i = idx % w - NG;
+    const int rest = idx / w, t = rest % (2 * NG);
+    k = rest / (2 * NG);
+    j = t < NG ? -1 - t : d.n2 + (t - NG);
+  } else if ((idx -= t2) < t3) {
+    i = idx % w - NG;
+    const int rest = idx / w, t = rest / h;
+    j = rest % h - NG;
+    k = t < NG ? -1 - t : d.n3 + (t - NG);
+  } else {
     return;
   }
-  const int src = type == GRMHD_BC_PERIODIC ? wrap(g, d.n3) : (side == 0 ? 0 : d.n3 - 1);
-  const int cs = cell_of(d, src, j, i);
-  for (int v = 0; v < NVAR; ++v) P[v * d.sv + cg] = P[v * d.sv + cs];
+  ghost_cell<NVAR, SCALAR>(p, d, cent, P, dsrc, i, j, k);
 }
 
 // ---- single-job kernels
 
-__global__ __launch_bounds__(256) void ghost_x1_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
-                                                       double* P, const double* dsrc) {
-  ghost_x1_body(p, d, cent, P, dsrc, (int)(blockIdx.x * blockDim.x + threadIdx.x));
-}
-__global__ __launch_bounds__(GB) void ghost_x2_kernel(grmhd_problem p, Dims d, double* P, const double* dsrc) {
-  ghost_x2_body(p, d, P, dsrc, (int)blockIdx.x);
-}
-__global__ __launch_bounds__(GB) void ghost_x3_kernel(grmhd_problem p, Dims d, double* P, const double* dsrc) {
-  ghost_x3_body(p, d, P, dsrc, (int)blockIdx.x);
+// all ghosts of a state in one launch; block 0 also clears the counters of
+// reset_mask (the step's ghost fill comes before the kernels that count)
+__global__ __launch_bounds__(256) void ghost_fill_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
+                                                         double* P, const double* dsrc, Counters* ctr,
+                                                         int reset_mask) {
+  if (ctr && blockIdx.x == 0 && threadIdx.x == 0) reset_counters(ctr, reset_mask);
+  ghost_fill_body(p, d, cent, P, dsrc, (int)(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
 // the two advected entropies of the electron-heating step
-__global__ __launch_bounds__(256) void scalar_ghost_x1_kernel(grmhd_problem p, Dims d, double* E, const double* dsrc) {
-  ghost_x1_body<GRMHD_NSCALAR, true>(p, d, nullptr, E, dsrc, (int)(blockIdx.x * blockDim.x + threadIdx.x));
-}
-__global__ __launch_bounds__(GB) void scalar_ghost_x2_kernel(grmhd_problem p, Dims d, double* E, const double* dsrc) {
-  ghost_x2_body<GRMHD_NSCALAR, true>(p, d, E, dsrc, (int)blockIdx.x);
-}
-__global__ __launch_bounds__(GB) void scalar_ghost_x3_kernel(grmhd_problem p, Dims d, double* E, const double* dsrc) {
-  ghost_x3_body<GRMHD_NSCALAR, true>(p, d, E, dsrc, (int)blockIdx.x);
+__global__ __launch_bounds__(256) void scalar_ghost_fill_kernel(grmhd_problem p, Dims d, double* E, const double* dsrc) {
+  ghost_fill_body<GRMHD_NSCALAR, true>(p, d, nullptr, E, dsrc, (int)(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
 // ---- batched kernels: the block finds its job, then runs the same body
 
-template <int DIR>
 __global__ __launch_bounds__(256) void ghost_batch_kernel(BatchView bv, int corrector) {
-  const int* offs = bv.offs + (PH_GHOST1 + DIR - 1) * (bv.njobs + 1);
+  const int* offs = bv.offs + PH_GHOST * (bv.njobs + 1);
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
   const int b = (int)blockIdx.x - offs[jb];
   double* tgt = global_ptr(corrector ? J.Ph : J.P);
   const double* src = global_ptr(J.P);
-  if (DIR == 1) ghost_x1_body(J.p, J.d, global_ptr(J.t.cent), tgt, src, b * (int)blockDim.x + (int)threadIdx.x);
-  else if (DIR == 2) ghost_x2_body(J.p, J.d, tgt, src, b);
-  else ghost_x3_body(J.p, J.d, tgt, src, b);
+  ghost_fill_body(J.p, J.d, global_ptr(J.t.cent), tgt, src, b * (int)blockDim.x + (int)threadIdx.x);
 }
 
 // the electron entropies of the jobs that have them: predictor fills E,
 // corrector E_h (Dirichlet ghosts from E)
-template <int DIR>
 __global__ __launch_bounds__(256) void scalar_ghost_batch_kernel(BatchView bv, int corrector) {
-  const int* offs = bv.offs + (PH_GHOST1 + DIR - 1) * (bv.njobs + 1);
+  const int* offs = bv.offs + PH_GHOST * (bv.njobs + 1);
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
   if (!J.E) return;
   const int b = (int)blockIdx.x - offs[jb];
   double* tgt = global_ptr(corrector ? J.Eh : J.E);
   const double* src = global_ptr(J.E);
-  if (DIR == 1) ghost_x1_body<GRMHD_NSCALAR, true>(J.p, J.d, nullptr, tgt, src, b * (int)blockDim.x + (int)threadIdx.x);
-  else if (DIR == 2) ghost_x2_body<GRMHD_NSCALAR, true>(J.p, J.d, tgt, src, b);
-  else ghost_x3_body<GRMHD_NSCALAR, true>(J.p, J.d, tgt, src, b);
+  ghost_fill_body<GRMHD_NSCALAR, true>(J.p, J.d, nullptr, tgt, src, b * (int)blockDim.x + (int)threadIdx.x);
 }
 
 // |corner-centred divergence of sqrt(-g) B| at corner (i, j, k), which sits at
@@ -307,24 +320,17 @@ dim3 divb_grid(const Dims& d) { return dim3((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.
 }  // namespace
 
 hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,
-                              const double* dsrc, hipStream_t s) {
-  const int n1threads = 2 * NG * d.n2 * d.n3;
-  hipLaunchKernelGGL(ghost_x1_kernel, dim3((n1threads + 255) / 256), dim3(256, 1, 1), 0, s, p, d, t.cent, P,
-                     dsrc);
-  const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
-  hipLaunchKernelGGL(ghost_x2_kernel, dim3(tiles * 2 * NG * d.n3), dim3(GB, 1, 1), 0, s, p, d, P, dsrc);
-  hipLaunchKernelGGL(ghost_x3_kernel, dim3(tiles * (d.n2 + 2 * NG) * 2 * NG), dim3(GB, 1, 1), 0, s, p, d, P, dsrc);
+                              const double* dsrc, hipStream_t s, Counters* ctr, int reset_mask) {
+  const int n = ghost_threads(d);
+  hipLaunchKernelGGL(ghost_fill_kernel, dim3((n + 255) / 256), dim3(256, 1, 1), 0, s, p, d, t.cent, P, dsrc, ctr,
+                     reset_mask);
   return hipGetLastError();
 }
 
 hipError_t launch_fill_scalar_ghosts(const grmhd_problem& p, const Dims& d, double* E, const double* dsrc,
                                      hipStream_t s) {
-  const int n1threads = 2 * NG * d.n2 * d.n3;
-  hipLaunchKernelGGL(scalar_ghost_x1_kernel, dim3((n1threads + 255) / 256), dim3(256, 1, 1), 0, s, p, d, E, dsrc);
-  const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
-  hipLaunchKernelGGL(scalar_ghost_x2_kernel, dim3(tiles * 2 * NG * d.n3), dim3(GB, 1, 1), 0, s, p, d, E, dsrc);
-  hipLaunchKernelGGL(scalar_ghost_x3_kernel, dim3(tiles * (d.n2 + 2 * NG) * 2 * NG), dim3(GB, 1, 1), 0, s, p, d, E,
-                     dsrc);
+  const int n = ghost_threads(d);
+  hipLaunchKernelGGL(scalar_ghost_fill_kernel, dim3((n + 255) / 256), dim3(256, 1, 1), 0, s, p, d, E, dsrc);
   return hipGetLastError();
 }
 
@@ -377,16 +383,12 @@ hipError_t launch_reset(Counters* ctr, int mask, hipStream_t s) {
 }
 
 hipError_t launch_batch_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s) {
-  hipLaunchKernelGGL(ghost_batch_kernel<1>, dim3(totals[PH_GHOST1]), dim3(256), 0, s, bv, corrector ? 1 : 0);
-  hipLaunchKernelGGL(ghost_batch_kernel<2>, dim3(totals[PH_GHOST2]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
-  hipLaunchKernelGGL(ghost_batch_kernel<3>, dim3(totals[PH_GHOST3]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
+  hipLaunchKernelGGL(ghost_batch_kernel, dim3(totals[PH_GHOST]), dim3(256), 0, s, bv, corrector ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_batch_scalar_ghosts(const BatchView& bv, const int* totals, bool corrector, hipStream_t s) {
-  hipLaunchKernelGGL(scalar_ghost_batch_kernel<1>, dim3(totals[PH_GHOST1]), dim3(256), 0, s, bv, corrector ? 1 : 0);
-  hipLaunchKernelGGL(scalar_ghost_batch_kernel<2>, dim3(totals[PH_GHOST2]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
-  hipLaunchKernelGGL(scalar_ghost_batch_kernel<3>, dim3(totals[PH_GHOST3]), dim3(GB), 0, s, bv, corrector ? 1 : 0);
+  hipLaunchKernelGGL(scalar_ghost_batch_kernel, dim3(totals[PH_GHOST]), dim3(256), 0, s, bv, corrector ? 1 : 0);
   return hipGetLastError();
 }
 
@@ -401,10 +403,7 @@ hipError_t launch_batch_dt(const BatchView& bv, hipStream_t s) {
 }
 
 void job_phase_blocks(const Dims& d, int counts[PH_COUNT]) {
-  counts[PH_GHOST1] = (2 * NG * d.n2 * d.n3 + 255) / 256;
-  const int tiles = (d.n1 + 2 * NG + GB - 1) / GB;
-  counts[PH_GHOST2] = tiles * 2 * NG * d.n3;
-  counts[PH_GHOST3] = tiles * (d.n2 + 2 * NG) * 2 * NG;
+  counts[PH_GHOST] = (ghost_threads(d) + 255) / 256;
   counts[PH_SWEEP] = (int)sweep_blocks(d);
   counts[PH_UPDATE] = (int)xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
 }

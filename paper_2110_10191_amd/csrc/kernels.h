@@ -68,7 +68,7 @@ struct JobDesc {
   double fel;
 };
 
-enum { PH_GHOST1 = 0, PH_GHOST2, PH_GHOST3, PH_SWEEP, PH_UPDATE, PH_COUNT };
+enum { PH_GHOST = 0, PH_SWEEP, PH_UPDATE, PH_COUNT };
 
 // offs[ph * (njobs + 1) + j] = first block of job j in phase ph; entry njobs = total
 struct BatchView {
@@ -125,7 +125,8 @@ hipError_t launch_batch_dt(const BatchView& bv, hipStream_t s);
 hipError_t launch_geometry(const grmhd_problem& p, const Dims& d, const Tables& t, hipStream_t s);
 
 hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,
-                              const double* dirichlet_src, hipStream_t s);
+                              const double* dirichlet_src, hipStream_t s, Counters* ctr = nullptr,
+                              int reset_mask = 0);
 
 // face fluxes of all three directions of state P into F[0..2] (double for
 // fp64, float for mixed); ctop (may be null) receives the per-direction

@@ -403,9 +403,18 @@ class Report:
 
 # ----------------------------------------------------------------- command line
 
-def identity_check(report, specs, make_state, recon, precision, sample, device="cuda:0", tiles=None):
+def _where_unequal(a, b):
+    """Count, largest difference and first indices of the entries of two
+    same-shape arrays that are not bitwise equal (NaN counts as unequal)."""
+    w = np.argwhere(~(a == b))
+    d = np.abs(a - b)
+    return {"count": int(len(w)), "max_abs": float(np.nanmax(d)) if d.size else 0.0, "first": w[:8].tolist()}
+
+
+def identity_check(report, specs, make_state, recon, precision, sample, device="cuda:0", tiles=None, diffs=None):
     """Re-run each sampled job alone and compare its final state bit for bit
-    with the state it reached inside the mix."""
+    with the state it reached inside the mix. diffs: a dict that receives, per
+    job that differs, where its arrays differ."""
     results = report.results()
     by_id = {s.id: s for s in specs}
     out = {}
@@ -424,6 +433,10 @@ def identity_check(report, specs, make_state, recon, precision, sample, device="
             out[jid] = isinstance(mixed, tuple) and all(np.array_equal(a, b) for a, b in zip(alone, mixed))
         else:
             out[jid] = bool(np.array_equal(alone, mixed))
+        if not out[jid] and diffs is not None:
+            pairs = zip(alone, mixed) if isinstance(alone, tuple) and isinstance(mixed, tuple) else [(alone, mixed)]
+            diffs[jid] = [_where_unequal(np.asarray(a), np.asarray(b)) for a, b in pairs
+                          if np.shape(a) == np.shape(b)]
     return out
 
 

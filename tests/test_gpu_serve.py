@@ -43,8 +43,9 @@ def test_stream_matches_jobs_run_alone(lib, recon, precision):
     assert srv.peak_in_use <= budget
     assert summ["p99_latency_s"] >= summ["p50_latency_s"] > 0
     assert srv.cycles >= 4
-    ident = identity_check(rep, specs, mk, recon, precision, [s.id for s in specs])
-    assert ident == {s.id: True for s in specs}
+    diffs = {}
+    ident = identity_check(rep, specs, mk, recon, precision, [s.id for s in specs], diffs=diffs)
+    assert ident == {s.id: True for s in specs}, diffs
 
 
 def test_a_job_that_cannot_start_is_failed_and_the_others_are_untouched(lib):
@@ -99,8 +100,9 @@ def test_stream_with_electron_heating_matches_jobs_run_alone(lib):
     assert rep.summary()["completed"] == 4 and not rep.failed
     res = rep.results()
     assert isinstance(res[0], tuple) and isinstance(res[3], tuple) and not isinstance(res[1], tuple)
-    ident = identity_check(rep, specs, mk, problems.RECON_MC, problems.FP64, [s.id for s in specs])
-    assert ident == {s.id: True for s in specs}
+    diffs = {}
+    ident = identity_check(rep, specs, mk, problems.RECON_MC, problems.FP64, [s.id for s in specs], diffs=diffs)
+    assert ident == {s.id: True for s in specs}, diffs
 
 
 def test_tuned_tiles_do_not_change_a_served_job(lib):
