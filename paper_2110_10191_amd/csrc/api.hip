@@ -178,7 +178,7 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
   }
   {
     ProfScope ps(c->prof, s, GRMHD_K_SWEEPS);
-    HIP_OR_FAIL(c, launch_sweeps(c->p.recon, c->mixed, c->d, c->t, c->p.gam, Ps, c->F, want_ctop ? c->ctr->ctop : nullptr,
+    HIP_OR_FAIL(c, launch_sweeps(c->p, c->mixed, c->d, c->t, Ps, c->F, want_ctop ? c->ctr->ctop : nullptr,
                                  s),
                 "sweeps");
   }
@@ -547,7 +547,7 @@ int grmhd_get_dt(grmhd_ctx* ctx, double* P, double* dt) {
   hipStream_t s = ctx->stream;
   HIP_OR_FAIL(ctx, launch_fill_ghosts(ctx->p, ctx->d, ctx->t, P, P, s), "ghost fill");
   HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 1, s), "reset");
-  HIP_OR_FAIL(ctx, launch_sweeps(ctx->p.recon, ctx->mixed, ctx->d, ctx->t, ctx->p.gam, P, ctx->F, ctx->ctr->ctop, s),
+  HIP_OR_FAIL(ctx, launch_sweeps(ctx->p, ctx->mixed, ctx->d, ctx->t, P, ctx->F, ctx->ctr->ctop, s),
               "sweeps");
   return read_dt(ctx, dt);
 }

@@ -7,6 +7,7 @@
 // change: Cartesian Kerr-Schild (metric eta + f l l in (t, x, y, z)) makes
 // every table depend on x3, so its tables are 3D with an x3-face table.
 #include "kernels.h"
+#include "cks_geometry.h"
 
 // No fused multiply-adds here: the connection's centred differences (step
 // 1e-5) turn a one-ulp change of the metric into a 1e-10 change of Gamma, so
@@ -50,17 +51,10 @@ __device__ void theta_derivs(double x1, double x2, const grmhd_problem& p, doubl
   d2 = dtg + e * (dtj - dtg);
 }
 
-// radius of a Cartesian Kerr-Schild point: the positive root r of
-// r^4 - (R^2 - a^2) r^2 - a^2 z^2 = 0, R^2 = x^2 + y^2 + z^2
-__device__ double cks_r(double x, double y, double z, double a) {
-  const double h = 0.5 * (x * x + y * y + z * z - a * a);
-  return sqrt(h + sqrt(h * h + a * a * z * z));
-}
-
 // Cartesian Kerr-Schild: g = eta + f l l with f = 2 r^3 / (r^4 + a^2 z^2) and
 // the null covector l = (1, (r x + a y)/(r^2 + a^2), (r y - a x)/(r^2 + a^2), z/r)
 __device__ void gcov_cks(double x, double y, double z, double a, double g[4][4]) {
-  const double r = cks_r(x, y, z, a);
+  const double r = cks_radius(x, y, z, a);
   const double r2 = r * r;
   const double f = 2.0 * r2 * r / (r2 * r2 + a * a * z * z);
   const double ra = r2 + a * a;
@@ -174,7 +168,21 @@ __device__ void store_point(double x1, double x2, double x3, const grmhd_problem
       for (int n = 0; n < 4; ++n) gcon_out[m][n] = gi[m][n];
 }
 
-__global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t) {
+// a face table entry (paired components) and its float copy
+__device__ void store_face(const Geo<double>& g, double* dt, float* ft, size_t ts, int off) {
+  for (int c = 0; c < 10; ++c) {
+    dt[pair_index(T_GCOV + c, ts, (size_t)off)] = g.gcov[c];
+    dt[pair_index(T_GCON + c, ts, (size_t)off)] = g.gcon[c];
+    ft[pair_index(T_GCOV + c, ts, (size_t)off)] = (float)g.gcov[c];
+    ft[pair_index(T_GCON + c, ts, (size_t)off)] = (float)g.gcon[c];
+  }
+  dt[pair_index(T_GDET, ts, (size_t)off)] = g.gdet;
+  dt[pair_index(T_ALPHA, ts, (size_t)off)] = g.alpha;
+  ft[pair_index(T_GDET, ts, (size_t)off)] = (float)g.gdet;
+  ft[pair_index(T_ALPHA, ts, (size_t)off)] = (float)g.alpha;
+}
+
+__global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t, CksBox box) {
   const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x) - NG;
   const int j = (int)(blockIdx.y * blockDim.y + threadIdx.y) - NG;
   const int k = (int)blockIdx.z - NG;  // 2D tables: a single plane (k = -NG, tk = 0)
@@ -185,16 +193,30 @@ __global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t) {
   const double dx2 = (p.x2max - p.x2min) / p.n2;
   const double dx3 = (p.x3max - p.x3min) / p.n3;
   const double x1c = p.x1min + (i + 0.5) * dx1, x2c = p.x2min + (j + 0.5) * dx2, x3c = p.x3min + (k + 0.5) * dx3;
-  const double x1f = p.x1min + i * dx1, x2f = p.x2min + j * dx2, x3f = p.x3min + k * dx3;
+  const double x1f = p.x1min + i * dx1, x2f = p.x2min + j * dx2;
   const bool k3 = p.coords == GRMHD_KERR_CKS;
 
   double gcon[4][4];
   store_point(x1c, x2c, x3c, p, t.cent, nullptr, ts, off, gcon);
-  store_point(x1f, x2c, x3c, p, t.f1, t.f1f, ts, off, nullptr);
-  store_point(x1c, x2f, x3c, p, t.f2, t.f2f, ts, off, nullptr);
-  // 2D tables: the metric does not depend on x3, and the x3-face table holds
-  // the centre values
-  store_point(x1c, x2c, k3 ? x3f : x3c, p, t.f3, t.f3f, ts, off, nullptr);
+  if (k3) {
+    // Cartesian Kerr-Schild faces in closed form, the values the face-flux
+    // pass computes itself
+    // box: the zone corner and widths the face-flux pass uses (computed on the host)
+    const CksBox& b = box;
+    double* const dt[3] = {t.f1, t.f2, t.f3};
+    float* const ft[3] = {t.f1f, t.f2f, t.f3f};
+    for (int D = 1; D <= 3; ++D) {
+      Geo<double> g;
+      cks_face_geo(b, D, i, j, k, g);
+      store_face(g, dt[D - 1], ft[D - 1], ts, off);
+    }
+  } else {
+    store_point(x1f, x2c, x3c, p, t.f1, t.f1f, ts, off, nullptr);
+    store_point(x1c, x2f, x3c, p, t.f2, t.f2f, ts, off, nullptr);
+    // 2D tables: the metric does not depend on x3, and the x3-face table
+    // holds the centre values
+    store_point(x1c, x2c, x3c, p, t.f3, t.f3f, ts, off, nullptr);
+  }
 
   // connection: Gamma_kmn = (d_n g_km + d_m g_kn - d_k g_mn)/2, Gamma^l_mn = g^lk Gamma_kmn,
   // derivatives by centred differences in x1, x2 and (3D tables) x3; d_t = 0
@@ -226,7 +248,7 @@ __global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t) {
   // Kerr-Schild radius of the Cartesian point
   double rfl = 0.0, ufl = 0.0;
   if (p.coords != GRMHD_MINKOWSKI_CART) {
-    const double r = k3 ? cks_r(x1c, x2c, x3c, p.a) : exp(x1c);
+    const double r = k3 ? cks_radius(x1c, x2c, x3c, p.a) : exp(x1c);
     const double kk = 1.0 / (r * r * (1.0 + r / 10.0));
     rfl = p.rho_fl * kk;
     ufl = p.u_fl * pow(kk, p.gam);
@@ -240,6 +262,6 @@ __global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t) {
 hipError_t launch_geometry(const grmhd_problem& p, const Dims& d, const Tables& t, hipStream_t s) {
   dim3 blk(64, 4, 1);
   dim3 grd((d.n1 + 2 * NG + 63) / 64, (d.n2 + 2 * NG + 3) / 4, d.tk ? d.p3 : 1);
-  hipLaunchKernelGGL(geometry_kernel, grd, blk, 0, s, p, d, t);
+  hipLaunchKernelGGL(geometry_kernel, grd, blk, 0, s, p, d, t, cks_box(p));
   return hipGetLastError();
 }

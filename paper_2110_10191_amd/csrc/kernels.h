@@ -129,10 +129,12 @@ hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Table
                               int reset_mask = 0);
 
 // face fluxes of all three directions of state P into F[0..2] (double for
-// fp64, float for mixed); ctop (may be null) receives the per-direction
-// maximum signal speeds; sweep_blocks: the launch's grid size
+// fp64, float for mixed) with the problem's reconstruction and gamma;
+// Cartesian Kerr-Schild computes its face geometry instead of reading the
+// face tables; ctop (may be null) receives the per-direction maximum signal
+// speeds; sweep_blocks: the launch's grid size
 unsigned sweep_blocks(const Dims& d);
-hipError_t launch_sweeps(int recon, bool mixed, const Dims& d, const Tables& t, double gam, const double* P,
+hipError_t launch_sweeps(const grmhd_problem& p, bool mixed, const Dims& d, const Tables& t, const double* P,
                          void* const* F, unsigned long long* ctop, hipStream_t s);
 
 // the step is dt, or dt_scale * *dt_dev when dt_dev is not null

@@ -18,9 +18,12 @@
 // per-direction maximum of ctop over the faces with interior transverse index
 // feeds the Courant step (one atomic max per block and direction); a face with
 // a NaN speed counts as +inf there, which the step reports as a non-finite
-// state.
+// state. The face geometry comes from the face tables, or for Cartesian
+// Kerr-Schild in FP64 from its closed form (the same bits as the table).
 #include <atomic>
+#include <type_traits>
 
+#include "cks_geometry.h"
 #include "kernels.h"
 
 namespace {
@@ -46,9 +49,12 @@ constexpr int halo_hi() { return RECON == GRMHD_RECON_MC ? 1 : 2; }
 // zero and nothing reads) and return the signal speed for the Courant maximum
 // (0 for a face with a transverse ghost index, +inf when its speeds are not
 // finite)
-template <int D, int RECON, typename T>
+// CKS: the face geometry of Cartesian Kerr-Schild computed in closed form
+// (the values of the face table) instead of read
+template <int D, int RECON, typename T, bool CKS>
 __device__ inline double one_face(const Dims& d, const double* __restrict__ P, const PlaneTile<T>& pt,
-                                  const T* __restrict__ tab, T* __restrict__ F, T gam, int i, int j, int k) {
+                                  const T* __restrict__ tab, const CksBox& box, T* __restrict__ F, T gam, int i,
+                                  int j, int k) {
   const int c = cell_of(d, k, j, i);
   T PL[NV], PR[NV];
 #pragma unroll
@@ -70,7 +76,8 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
     }
   }
   Geo<T> g;
-  load_face_geo(g, face_plane(tab, d, k), d.ts, tab_of(d, j, i));
+  if constexpr (CKS) cks_face_geo(box, D, i, j, k, g);
+  else load_face_geo(g, face_plane(tab, d, k), d.ts, tab_of(d, j, i));
   T FL[NV], UL[NV], cpL, cmL;
   {
     Fluid<T> f;
@@ -114,10 +121,10 @@ __device__ inline double one_face(const Dims& d, const double* __restrict__ P, c
 
 // b: block index within this job's grid of tiles over (n1+2) x (n2+2) x (n3+2)
 // cells starting at (-1, -1, -1)
-template <int RECON, typename T>
+template <int RECON, typename T, bool CKS = false>
 __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T* __restrict__ t1,
-                           const T* __restrict__ t2, const T* __restrict__ t3, T* __restrict__ F1, T* __restrict__ F2,
-                           T* __restrict__ F3, T gam, int b, unsigned long long* ctop) {
+                           const T* __restrict__ t2, const T* __restrict__ t3, const CksBox& box, T* __restrict__ F1,
+                           T* __restrict__ F2, T* __restrict__ F3, T gam, int b, unsigned long long* ctop) {
   const TileK t = xcd_tile_k(b, d.stx, d.sty, d.n1 + 2, d.n3 + 2);
   const int i = -1 + t.i0 + (int)threadIdx.x;
   const int j = -1 + t.j0 + (int)threadIdx.y;
@@ -150,18 +157,18 @@ __device__ void sweep_body(const Dims& d, const double* __restrict__ P, const T*
   }
   __syncthreads();
   double c1 = 0.0, c2 = 0.0, c3 = 0.0;
-  if (ok && i >= 0) c1 = one_face<1, RECON, T>(d, P, pt, t1, F1, gam, i, j, k);
-  if (ok && j >= 0) c2 = one_face<2, RECON, T>(d, P, pt, t2, F2, gam, i, j, k);
-  if (ok && k >= 0) c3 = one_face<3, RECON, T>(d, P, pt, t3, F3, gam, i, j, k);
+  if (ok && i >= 0) c1 = one_face<1, RECON, T, CKS>(d, P, pt, t1, box, F1, gam, i, j, k);
+  if (ok && j >= 0) c2 = one_face<2, RECON, T, CKS>(d, P, pt, t2, box, F2, gam, i, j, k);
+  if (ok && k >= 0) c3 = one_face<3, RECON, T, CKS>(d, P, pt, t3, box, F3, gam, i, j, k);
   if (ctop) block_max3_to(c1, c2, c3, ctop);
 }
 
-template <int RECON, typename T>
+template <int RECON, typename T, bool CKS>
 __global__ __launch_bounds__(512) void sweep_kernel(Dims d, const double* __restrict__ P, const T* __restrict__ t1,
-                                                    const T* __restrict__ t2, const T* __restrict__ t3,
+                                                    const T* __restrict__ t2, const T* __restrict__ t3, CksBox box,
                                                     T* __restrict__ F1, T* __restrict__ F2, T* __restrict__ F3, T gam,
                                                     unsigned long long* ctop) {
-  sweep_body<RECON, T>(d, P, t1, t2, t3, F1, F2, F3, gam, (int)blockIdx.x, ctop);
+  sweep_body<RECON, T, CKS>(d, P, t1, t2, t3, box, F1, F2, F3, gam, (int)blockIdx.x, ctop);
 }
 
 template <typename T>
@@ -185,8 +192,9 @@ __global__ __launch_bounds__(512) void sweep_batch_kernel(BatchView bv, int corr
   const int* offs = bv.offs + PH_SWEEP * (bv.njobs + 1);
   const int jb = batch_job(offs, bv.njobs, (int)blockIdx.x);
   const JobDesc& J = bv.jobs[jb];
+  const CksBox none{};
   sweep_body<RECON, T>(J.d, global_ptr(corrector ? J.Ph : J.P), global_ptr(FaceTables<T>::f1(J.t)),
-                       global_ptr(FaceTables<T>::f2(J.t)), global_ptr(FaceTables<T>::f3(J.t)),
+                       global_ptr(FaceTables<T>::f2(J.t)), global_ptr(FaceTables<T>::f3(J.t)), none,
                        global_ptr((T*)J.F[0]), global_ptr((T*)J.F[1]), global_ptr((T*)J.F[2]), (T)J.p.gam,
                        (int)blockIdx.x - offs[jb], want_ctop ? global_ptr(J.ctr->ctop) : nullptr);
 }
@@ -212,17 +220,29 @@ hipError_t allow_lds(size_t bytes) {
   return e;
 }
 
-template <int RECON, typename T>
-hipError_t launch_for(const Dims& d, const Tables& t, double gam, const double* P, void* const* F,
-                      unsigned long long* ctop, hipStream_t s) {
+template <int RECON, typename T, bool CKS>
+hipError_t launch_geo(const Dims& d, const Tables& t, const CksBox& box, double gam, const double* P,
+                      void* const* F, unsigned long long* ctop, hipStream_t s) {
   const unsigned nblk = sweep_blocks(d);
   const size_t lds = tile_bytes<RECON, T>(d.stx, d.sty);
-  const hipError_t e = allow_lds<sweep_kernel<RECON, T>>(lds);
+  const hipError_t e = allow_lds<sweep_kernel<RECON, T, CKS>>(lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((sweep_kernel<RECON, T>), dim3(nblk), dim3(d.stx, d.sty, 1), lds, s, d, P,
-                     FaceTables<T>::f1(t), FaceTables<T>::f2(t), FaceTables<T>::f3(t), (T*)F[0], (T*)F[1],
+  hipLaunchKernelGGL((sweep_kernel<RECON, T, CKS>), dim3(nblk), dim3(d.stx, d.sty, 1), lds, s, d, P,
+                     FaceTables<T>::f1(t), FaceTables<T>::f2(t), FaceTables<T>::f3(t), box, (T*)F[0], (T*)F[1],
                      (T*)F[2], (T)gam, ctop);
   return hipGetLastError();
+}
+
+// Cartesian Kerr-Schild in FP64 computes its face geometry instead of
+// streaming the 3D face tables (a third of the bytes the pass moves); the
+// FP32 pass reads the float tables, cheaper than evaluating the metric in
+// FP64; the other coordinates read their 2D tables
+template <int RECON, typename T>
+hipError_t launch_for(const grmhd_problem& p, const Dims& d, const Tables& t, const double* P, void* const* F,
+                      unsigned long long* ctop, hipStream_t s) {
+  if (std::is_same<T, double>::value && p.coords == GRMHD_KERR_CKS)
+    return launch_geo<RECON, T, true>(d, t, cks_box(p), p.gam, P, F, ctop, s);
+  return launch_geo<RECON, T, false>(d, t, CksBox{}, p.gam, P, F, ctop, s);
 }
 
 template <int RECON, typename T>
@@ -238,14 +258,14 @@ hipError_t launch_batch_for(const BatchView& bv, dim3 grd, dim3 blk, int c, int 
 
 unsigned sweep_blocks(const Dims& d) { return xcd_grid(d.n1 + 2, d.n2 + 2, d.n3 + 2, d.stx, d.sty); }
 
-hipError_t launch_sweeps(int recon, bool mixed, const Dims& d, const Tables& t, double gam, const double* P,
+hipError_t launch_sweeps(const grmhd_problem& p, bool mixed, const Dims& d, const Tables& t, const double* P,
                          void* const* F, unsigned long long* ctop, hipStream_t s) {
   if (mixed) {
-    if (recon == GRMHD_RECON_MC) return launch_for<GRMHD_RECON_MC, float>(d, t, gam, P, F, ctop, s);
-    return launch_for<GRMHD_RECON_WENO5, float>(d, t, gam, P, F, ctop, s);
+    if (p.recon == GRMHD_RECON_MC) return launch_for<GRMHD_RECON_MC, float>(p, d, t, P, F, ctop, s);
+    return launch_for<GRMHD_RECON_WENO5, float>(p, d, t, P, F, ctop, s);
   }
-  if (recon == GRMHD_RECON_MC) return launch_for<GRMHD_RECON_MC, double>(d, t, gam, P, F, ctop, s);
-  return launch_for<GRMHD_RECON_WENO5, double>(d, t, gam, P, F, ctop, s);
+  if (p.recon == GRMHD_RECON_MC) return launch_for<GRMHD_RECON_MC, double>(p, d, t, P, F, ctop, s);
+  return launch_for<GRMHD_RECON_WENO5, double>(p, d, t, P, F, ctop, s);
 }
 
 hipError_t launch_batch_sweeps(const BatchView& bv, const int* totals, int recon, bool mixed, bool corrector,
