@@ -4,7 +4,7 @@
  * conservative finite-volume scheme that iharm3D implements.
  *
  * What the calls compute (the problem as the paper states it):
- *   - ideal GRMHD on a logically Cartesian mesh in arbitrary coordinates of a
+ *   - ideal GRMHD on a mesh uniform in code coordinates (any coordinates) of a
  *     stationary metric whose line element is analytic (Functionality section;
  *     Implementation Notes: metric quantities evaluated numerically);
  *   - units GM = c = 1 (Implementation Notes);

@@ -1,7 +1,7 @@
 """Boundaries, fluxes, Flux-CT, update, bounds, time step and driver (oracle).
 
-Functionality section: HARM is a conservative finite-volume scheme on a
-logically Cartesian mesh. One step of the method, as this oracle evaluates it
+Functionality section: HARM updates conserved variables by finite volumes
+on a mesh that is uniform in its code coordinates. One step of the method, as this oracle evaluates it
 (the paper defers the scheme to the HARM papers; the readings are stated where
 they are taken):
 

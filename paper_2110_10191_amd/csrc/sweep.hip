@@ -4,8 +4,8 @@
 // magnetosonic speeds) and combine them with the local Lax-Friedrichs flux
 //   F = (F_L + F_R)/2 - ctop (U_R - U_L)/2,
 //   ctop = max(max(0, c+_L, c+_R), max(0, -c-_L, -c-_R)).
-// Functionality section: HARM is a conservative finite-volume scheme; the
-// reconstruction and Riemann solver follow the HARM literature.
+// Functionality section: HARM updates conserved variables by finite volumes;
+// the reconstruction and Riemann solver follow the HARM literature.
 //
 // Faces covered in direction d: 0..n_d along d, and -1..n_t in both
 // transverse directions (the extra transverse layer feeds the Flux-CT EMFs).

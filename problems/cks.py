@@ -2,8 +2,8 @@
 
 This workload uses a spacetime whose metric depends on all three code
 coordinates. The code coordinates are the Cartesian Kerr-Schild (x, y, z). The
-paper calls such a change of coordinate system or background spacetime a
-trivial modification (Implementation Notes).
+Implementation Notes treat a new set of coordinates or a new stationary
+background as a small change, since only the metric evaluation differs.
 
 * Position. The Boyer-Lindquist-like radius r is the positive root of
   r^4 - (R^2 - a^2) r^2 - a^2 z^2 = 0, with cos theta = z / r and

@@ -1,7 +1,7 @@
 """Cartesian Kerr-Schild through the C ABI against the oracle.
 
 The metric depends on all three code coordinates (Implementation Notes: a
-change of coordinate system or background spacetime), so the geometry tables
+change of coordinates or of the stationary background), so the geometry tables
 are 3D and the x3 faces have a table of their own. The workload is a
 magnetised Michel flow on a box off the hole with a = 0.9375, Dirichlet
 boundaries on all six sides and floors on. The box is 40 x 28 x 20: the
