@@ -31,7 +31,8 @@ bounded sample of the same torus.
 
 ``--coords cks`` times another workload instead: a magnetised Michel flow on a
 168^3 Cartesian Kerr-Schild box, whose geometry tables are 3D (every zone
-reads its own metric and connection, 2400 B per zone-cycle compulsory).
+reads its own metric and connection: 1344 B per zone-cycle compulsory in
+FP64, where the face metric is evaluated in closed form).
 
 Prints one JSON line on stdout.
 """
@@ -59,12 +60,14 @@ def compulsory_bytes_per_zone_cycle(prm):
     axisymmetric geometry, about 150 doubles per (x1, x2) column per substep,
     shared by the n3 zones of the column. 338.75 B on the 288 x 128 x 128 torus.
     Cartesian Kerr-Schild geometry depends on x3, so every zone reads its own
-    tables each substep: the centre table (64 values: metric, inverse,
-    sqrt(-g), lapse, connection, floor scales) and three face tables (22
-    values each; float in mixed precision)."""
+    centre table each substep (64 values: metric, inverse, sqrt(-g), lapse,
+    the connection by centred differences, floor scales); its face metric has
+    a closed form that the FP64 face-flux pass evaluates instead of reading,
+    while the mixed-precision pass reads the float face tables (3 x 22
+    values)."""
     if prm["coords"] == CKS:
-        face = 4 if prm["precision"] == 1 else 8
-        return 320.0 + 2 * (64 * 8 + 3 * 22 * face)
+        faces = 3 * 22 * 4 if prm["precision"] == 1 else 0
+        return 320.0 + 2 * (64 * 8 + faces)
     geo = 0.0 if prm["coords"] == 0 else 2 * 150 * 8 / prm["n3"]
     return 320.0 + geo
 

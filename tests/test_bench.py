@@ -21,11 +21,11 @@ def test_compulsory_bytes_per_zone_cycle():
     assert bench.compulsory_bytes_per_zone_cycle(prm) == 338.75
     # Minkowski: no geometry
     assert bench.compulsory_bytes_per_zone_cycle(dict(prm, coords=problems.MINKOWSKI_CART)) == 320.0
-    # Cartesian Kerr-Schild: every zone's centre table (64 values) and three
-    # face tables (22 values each) per substep; the face tables in float for
-    # mixed precision
+    # Cartesian Kerr-Schild: every zone's centre table (64 values) per
+    # substep; the FP64 face-flux pass evaluates the face metric in closed
+    # form, the mixed one reads the three float face tables (22 values each)
     cks = dict(coords=problems.KERR_CKS, n3=168, precision=problems.FP64)
-    assert bench.compulsory_bytes_per_zone_cycle(cks) == 320 + 2 * (64 * 8 + 3 * 22 * 8) == 2400
+    assert bench.compulsory_bytes_per_zone_cycle(cks) == 320 + 2 * 64 * 8 == 1344
     assert bench.compulsory_bytes_per_zone_cycle(dict(cks, precision=problems.MIXED)) == 320 + 2 * (64 * 8 + 3 * 22 * 4)
 
 
