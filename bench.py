@@ -31,8 +31,8 @@ bounded sample of the same torus.
 
 ``--coords cks`` times another workload instead: a magnetised Michel flow on a
 168^3 Cartesian Kerr-Schild box, whose geometry tables are 3D (every zone
-reads its own metric and connection: 1344 B per zone-cycle compulsory in
-FP64, where the face metric is evaluated in closed form).
+reads its own connection: 992 B per zone-cycle compulsory in FP64, where
+the metric is evaluated in closed form).
 
 Prints one JSON line on stdout.
 """
@@ -60,14 +60,16 @@ def compulsory_bytes_per_zone_cycle(prm):
     axisymmetric geometry, about 150 doubles per (x1, x2) column per substep,
     shared by the n3 zones of the column. 338.75 B on the 288 x 128 x 128 torus.
     Cartesian Kerr-Schild geometry depends on x3, so every zone reads its own
-    centre table each substep (64 values: metric, inverse, sqrt(-g), lapse,
-    the connection by centred differences, floor scales); its face metric has
-    a closed form that the FP64 face-flux pass evaluates instead of reading,
-    while the mixed-precision pass reads the float face tables (3 x 22
-    values)."""
+    connection (40 values, by centred differences) and floor scales (2) each
+    substep; the metric, its inverse, sqrt(-g) and the lapse have closed
+    forms that the FP64 kernels evaluate instead of reading (at the centre
+    and at the faces), while in mixed precision the update reads the whole
+    centre table (64 values) and the face-flux pass the float face tables
+    (3 x 22 values)."""
     if prm["coords"] == CKS:
-        faces = 3 * 22 * 4 if prm["precision"] == 1 else 0
-        return 320.0 + 2 * (64 * 8 + faces)
+        if prm["precision"] == 1:
+            return 320.0 + 2 * (64 * 8 + 3 * 22 * 4)
+        return 320.0 + 2 * (42 * 8)
     geo = 0.0 if prm["coords"] == 0 else 2 * 150 * 8 / prm["n3"]
     return 320.0 + geo
 

@@ -192,7 +192,8 @@ int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool 
   {
     ProfScope ps(c->prof, s, GRMHD_K_UPDATE);
     HIP_OR_FAIL(c, launch_update(c->mixed, c->d, c->t, c->up, c->F[0], c->F[1], c->F[2], Pb, Ps, Pout,
-                                 fl, dt, dt_dev, dt_scale, c->ctr, s),
+                                 fl, dt, dt_dev, dt_scale, c->ctr, s,
+                                 c->p.coords == GRMHD_KERR_CKS ? &c->p : nullptr),
                 "update");
   }
   if (fix) {

@@ -1,6 +1,6 @@
-// Cartesian Kerr-Schild geometry of a face point in closed form, for the
-// face tables and for the face-flux pass that computes it instead of reading
-// them. Implementation Notes section: a change of coordinates or background
+// Cartesian Kerr-Schild geometry of a point in closed form, for the face
+// tables and the metric part of the centre table, and for the face-flux pass
+// and the update, which compute it instead of reading it. Implementation Notes section: a change of coordinates or background
 // spacetime only changes the metric evaluation. The metric is
 // g = eta + f l l with f = 2 r^3 / (r^4 + a^2 z^2) and the covector
 // l = (1, (r x + a y)/(r^2 + a^2), (r y - a x)/(r^2 + a^2), z/r), null for
@@ -38,15 +38,11 @@ __device__ inline double cks_radius(double x, double y, double z, double a) {
   return sqrt(h + sqrt(h * h + a * a * z * z));
 }
 
-// metric, inverse, sqrt(-g) and lapse at the lower D-face (D = 1..3) of cell
-// (i, j, k); double precision, stored as T
+// metric, inverse, sqrt(-g) and lapse at the point (x, y, z); double
+// precision, stored as T
 template <typename T>
-__device__ inline void cks_face_geo(const CksBox& b, int D, int i, int j, int k, Geo<T>& g) {
+__device__ inline void cks_point_geo(double x, double y, double z, double a, Geo<T>& g) {
 #pragma clang fp contract(off)
-  const double x = b.x0[0] + (D == 1 ? (double)i : i + 0.5) * b.dx[0];
-  const double y = b.x0[1] + (D == 2 ? (double)j : j + 0.5) * b.dx[1];
-  const double z = b.x0[2] + (D == 3 ? (double)k : k + 0.5) * b.dx[2];
-  const double a = b.a;
   const double r = cks_radius(x, y, z, a);
   const double r2 = r * r;
   const double f = 2.0 * r2 * r / (r2 * r2 + a * a * z * z);
@@ -69,4 +65,24 @@ __device__ inline void cks_face_geo(const CksBox& b, int D, int i, int j, int k,
   asm volatile("" : "+v"(one));
   g.gdet = (T)one;
   g.alpha = (T)(1.0 / sqrt(1.0 + f));
+}
+
+// at the lower D-face (D = 1..3) of cell (i, j, k)
+template <typename T>
+__device__ inline void cks_face_geo(const CksBox& b, int D, int i, int j, int k, Geo<T>& g) {
+#pragma clang fp contract(off)
+  const double x = b.x0[0] + (D == 1 ? (double)i : i + 0.5) * b.dx[0];
+  const double y = b.x0[1] + (D == 2 ? (double)j : j + 0.5) * b.dx[1];
+  const double z = b.x0[2] + (D == 3 ? (double)k : k + 0.5) * b.dx[2];
+  cks_point_geo(x, y, z, b.a, g);
+}
+
+// at the centre of cell (i, j, k)
+template <typename T>
+__device__ inline void cks_centre_geo(const CksBox& b, int i, int j, int k, Geo<T>& g) {
+#pragma clang fp contract(off)
+  const double x = b.x0[0] + (i + 0.5) * b.dx[0];
+  const double y = b.x0[1] + (j + 0.5) * b.dx[1];
+  const double z = b.x0[2] + (k + 0.5) * b.dx[2];
+  cks_point_geo(x, y, z, b.a, g);
 }

@@ -197,7 +197,22 @@ __global__ void geometry_kernel(grmhd_problem p, Dims d, Tables t, CksBox box) {
   const bool k3 = p.coords == GRMHD_KERR_CKS;
 
   double gcon[4][4];
-  store_point(x1c, x2c, x3c, p, t.cent, nullptr, ts, off, gcon);
+  if (k3) {
+    // Cartesian Kerr-Schild centres in closed form, the values the update
+    // computes itself (the connection below uses this inverse)
+    Geo<double> g;
+    cks_centre_geo(box, i, j, k, g);
+    for (int c = 0; c < 10; ++c) {
+      t.cent[(size_t)(T_GCOV + c) * ts + off] = g.gcov[c];
+      t.cent[(size_t)(T_GCON + c) * ts + off] = g.gcon[c];
+    }
+    t.cent[(size_t)T_GDET * ts + off] = g.gdet;
+    t.cent[(size_t)T_ALPHA * ts + off] = g.alpha;
+    for (int m = 0; m < 4; ++m)
+      for (int n = 0; n < 4; ++n) gcon[m][n] = g.gcon[sidx(m, n)];
+  } else {
+    store_point(x1c, x2c, x3c, p, t.cent, nullptr, ts, off, gcon);
+  }
   if (k3) {
     // Cartesian Kerr-Schild faces in closed form, the values the face-flux
     // pass computes itself

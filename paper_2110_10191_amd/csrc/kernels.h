@@ -137,11 +137,14 @@ unsigned sweep_blocks(const Dims& d);
 hipError_t launch_sweeps(const grmhd_problem& p, bool mixed, const Dims& d, const Tables& t, const double* P,
                          void* const* F, unsigned long long* ctop, hipStream_t s);
 
-// the step is dt, or dt_scale * *dt_dev when dt_dev is not null
+// the step is dt, or dt_scale * *dt_dev when dt_dev is not null; cks (the
+// problem, Cartesian Kerr-Schild only): the FP64 update computes the centre
+// metric in closed form instead of reading it
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up,
                          const void* F1, const void* F2, const void* F3, const double* Pb,
                          const double* Ps, double* Pout, int8_t* flags, double dt,
-                         const double* dt_dev, double dt_scale, Counters* ctr, hipStream_t s);
+                         const double* dt_dev, double dt_scale, Counters* ctr, hipStream_t s,
+                         const grmhd_problem* cks = nullptr);
 
 // ctr->dt <- min(cfl / sum_d(ctop_d / dx_d), 1.3 ctr->dt) on the device
 hipError_t launch_ctx_dt(Counters* ctr, double cfl, double dx1, double dx2, double dx3, hipStream_t s);

@@ -25,6 +25,7 @@
 // rho >= u/uorho_max; k = 1/(r^2 (1 + r/10)).
 #include <type_traits>
 
+#include "cks_geometry.h"
 #include "kernels.h"
 
 namespace {
@@ -143,8 +144,11 @@ struct FluxView {
 };
 
 // b: block index within this job's grid (the update tile d.utx x d.uty, XCD-aware order)
-template <typename TF, bool EARLY_PS = false>
-__device__ void update_body(const Dims& d, const double* __restrict__ cent, const UpdateParams& up,
+// CKS: the centre metric of Cartesian Kerr-Schild computed in closed form
+// (the values of the centre table) instead of read; the connection and the
+// floor scales still come from the table
+template <typename TF, bool EARLY_PS = false, bool CKS = false>
+__device__ void update_body(const Dims& d, const double* __restrict__ cent, const CksBox& box, const UpdateParams& up,
                             const TF* __restrict__ F1p, const TF* __restrict__ F2p, const TF* __restrict__ F3p,
                             const double* Pb, const double* __restrict__ Ps, double* Pout,
                             int8_t* __restrict__ flags, double dt, Counters* ctr, int b) {
@@ -213,7 +217,8 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
     const int toff = tab_of(d, j, i);
     const double* ck = tab_plane(cent, d, k);
     Geo<double> g;
-    load_geo(g, ck, d.ts, toff);
+    if constexpr (CKS) cks_centre_geo(box, i, j, k, g);
+    else load_geo(g, ck, d.ts, toff);
     if (!EARLY_PS) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) ps[v] = Ps[v * d.sv + c];
@@ -268,8 +273,8 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
 // Left free the compiler takes 224 (two waves) and the kernel waits on its
 // loads and long dependency chains with too little to switch to; the FP64
 // variant fits 168 without spilling.
-template <typename TF, bool DEV_DT>
-__global__ __launch_bounds__(256, 3) void update_kernel(Dims d, const double* __restrict__ cent, UpdateParams up,
+template <typename TF, bool DEV_DT, bool CKS = false>
+__global__ __launch_bounds__(256, 3) void update_kernel(Dims d, const double* __restrict__ cent, CksBox box, UpdateParams up,
                                                      const TF* __restrict__ F1, const TF* __restrict__ F2,
                                                      const TF* __restrict__ F3, const double* Pb,
                                                      const double* __restrict__ Ps, double* Pout,
@@ -277,7 +282,7 @@ __global__ __launch_bounds__(256, 3) void update_kernel(Dims d, const double* __
                                                      const double* __restrict__ dt_dev, double dt_scale,
                                                      Counters* ctr) {
   if (DEV_DT) dt = dt_scale * *dt_dev;
-  update_body<TF>(d, cent, up, F1, F2, F3, Pb, Ps, Pout, flags, dt, ctr, (int)blockIdx.x);
+  update_body<TF, false, CKS>(d, cent, box, up, F1, F2, F3, Pb, Ps, Pout, flags, dt, ctr, (int)blockIdx.x);
 }
 
 // every job of a batch: predictor P -> P_h with dt/2, corrector (P, P_h) -> P with dt
@@ -289,7 +294,7 @@ __global__ __launch_bounds__(256, 3) void update_batch_kernel(BatchView bv, int 
   const double dt = corrector ? *J.dt : 0.5 * *J.dt;
   // the FP64 batch variant runs faster with the source state loaded first (and
   // without spilling); the float-flux one and the single-job kernels slower
-  update_body<TF, std::is_same<TF, double>::value>(J.d, global_ptr(J.t.cent), J.up, global_ptr((const TF*)J.F[0]), global_ptr((const TF*)J.F[1]),
+  update_body<TF, std::is_same<TF, double>::value>(J.d, global_ptr(J.t.cent), CksBox{}, J.up, global_ptr((const TF*)J.F[0]), global_ptr((const TF*)J.F[1]),
                   global_ptr((const TF*)J.F[2]), global_ptr(J.P), global_ptr(corrector ? J.Ph : J.P),
                   global_ptr(corrector ? J.P : J.Ph), global_ptr(J.flags), dt, global_ptr(J.ctr),
                   (int)blockIdx.x - offs[jb]);
@@ -421,24 +426,31 @@ __global__ __launch_bounds__(256) void u2p_kernel(Dims d, const double* __restri
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up, const void* F1,
                          const void* F2, const void* F3, const double* Pb, const double* Ps, double* Pout,
                          int8_t* flags, double dt, const double* dt_dev, double dt_scale, Counters* ctr,
-                         hipStream_t s) {
+                         hipStream_t s, const grmhd_problem* cks) {
   const unsigned nblk = xcd_grid(d.n1, d.n2, d.n3, d.utx, d.uty);
   dim3 blk(d.utx, d.uty, 1), grd(nblk);
+  const CksBox box = cks ? cks_box(*cks) : CksBox{};
   if (mixed) {
     const float *f1 = (const float*)F1, *f2 = (const float*)F2, *f3 = (const float*)F3;
     if (dt_dev)
-      hipLaunchKernelGGL((update_kernel<float, true>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+      hipLaunchKernelGGL((update_kernel<float, true>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps, Pout,
                          flags, dt, dt_dev, dt_scale, ctr);
     else
-      hipLaunchKernelGGL((update_kernel<float, false>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+      hipLaunchKernelGGL((update_kernel<float, false>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps, Pout,
                          flags, dt, dt_dev, dt_scale, ctr);
   } else {
     const double *f1 = (const double*)F1, *f2 = (const double*)F2, *f3 = (const double*)F3;
-    if (dt_dev)
-      hipLaunchKernelGGL((update_kernel<double, true>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+    if (cks && dt_dev)
+      hipLaunchKernelGGL((update_kernel<double, true, true>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps,
+                         Pout, flags, dt, dt_dev, dt_scale, ctr);
+    else if (cks)
+      hipLaunchKernelGGL((update_kernel<double, false, true>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps,
+                         Pout, flags, dt, dt_dev, dt_scale, ctr);
+    else if (dt_dev)
+      hipLaunchKernelGGL((update_kernel<double, true>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps, Pout,
                          flags, dt, dt_dev, dt_scale, ctr);
     else
-      hipLaunchKernelGGL((update_kernel<double, false>), grd, blk, 0, s, d, t.cent, up, f1, f2, f3, Pb, Ps, Pout,
+      hipLaunchKernelGGL((update_kernel<double, false>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps, Pout,
                          flags, dt, dt_dev, dt_scale, ctr);
   }
   return hipGetLastError();

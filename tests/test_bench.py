@@ -21,11 +21,12 @@ def test_compulsory_bytes_per_zone_cycle():
     assert bench.compulsory_bytes_per_zone_cycle(prm) == 338.75
     # Minkowski: no geometry
     assert bench.compulsory_bytes_per_zone_cycle(dict(prm, coords=problems.MINKOWSKI_CART)) == 320.0
-    # Cartesian Kerr-Schild: every zone's centre table (64 values) per
-    # substep; the FP64 face-flux pass evaluates the face metric in closed
-    # form, the mixed one reads the three float face tables (22 values each)
+    # Cartesian Kerr-Schild: every zone's connection and floor scales (42
+    # values) per substep, the metric evaluated in closed form in FP64; in
+    # mixed precision the whole centre table (64 values) and the three float
+    # face tables (22 values each)
     cks = dict(coords=problems.KERR_CKS, n3=168, precision=problems.FP64)
-    assert bench.compulsory_bytes_per_zone_cycle(cks) == 320 + 2 * 64 * 8 == 1344
+    assert bench.compulsory_bytes_per_zone_cycle(cks) == 320 + 2 * 42 * 8 == 992
     assert bench.compulsory_bytes_per_zone_cycle(dict(cks, precision=problems.MIXED)) == 320 + 2 * (64 * 8 + 3 * 22 * 4)
 
 
