@@ -62,14 +62,12 @@ def compulsory_bytes_per_zone_cycle(prm):
     Cartesian Kerr-Schild geometry depends on x3, so every zone reads its own
     connection (40 values, by centred differences) and floor scales (2) each
     substep; the metric, its inverse, sqrt(-g) and the lapse have closed
-    forms that the FP64 kernels evaluate instead of reading (at the centre
-    and at the faces), while in mixed precision the update reads the whole
-    centre table (64 values) and the face-flux pass the float face tables
-    (3 x 22 values)."""
+    forms that the kernels evaluate instead of reading (the update at the
+    centre; the FP64 face-flux pass at the faces, while the mixed-precision
+    one reads the float face tables, 3 x 22 values)."""
     if prm["coords"] == CKS:
-        if prm["precision"] == 1:
-            return 320.0 + 2 * (64 * 8 + 3 * 22 * 4)
-        return 320.0 + 2 * (42 * 8)
+        faces = 3 * 22 * 4 if prm["precision"] == 1 else 0
+        return 320.0 + 2 * (42 * 8 + faces)
     geo = 0.0 if prm["coords"] == 0 else 2 * 150 * 8 / prm["n3"]
     return 320.0 + geo
 

@@ -138,7 +138,7 @@ hipError_t launch_sweeps(const grmhd_problem& p, bool mixed, const Dims& d, cons
                          void* const* F, unsigned long long* ctop, hipStream_t s);
 
 // the step is dt, or dt_scale * *dt_dev when dt_dev is not null; cks (the
-// problem, Cartesian Kerr-Schild only): the FP64 update computes the centre
+// problem, Cartesian Kerr-Schild only): the update computes the centre
 // metric in closed form instead of reading it
 hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const UpdateParams& up,
                          const void* F1, const void* F2, const void* F3, const double* Pb,

@@ -432,7 +432,13 @@ hipError_t launch_update(bool mixed, const Dims& d, const Tables& t, const Updat
   const CksBox box = cks ? cks_box(*cks) : CksBox{};
   if (mixed) {
     const float *f1 = (const float*)F1, *f2 = (const float*)F2, *f3 = (const float*)F3;
-    if (dt_dev)
+    if (cks && dt_dev)
+      hipLaunchKernelGGL((update_kernel<float, true, true>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps,
+                         Pout, flags, dt, dt_dev, dt_scale, ctr);
+    else if (cks)
+      hipLaunchKernelGGL((update_kernel<float, false, true>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps,
+                         Pout, flags, dt, dt_dev, dt_scale, ctr);
+    else if (dt_dev)
       hipLaunchKernelGGL((update_kernel<float, true>), grd, blk, 0, s, d, t.cent, box, up, f1, f2, f3, Pb, Ps, Pout,
                          flags, dt, dt_dev, dt_scale, ctr);
     else

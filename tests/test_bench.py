@@ -22,12 +22,11 @@ def test_compulsory_bytes_per_zone_cycle():
     # Minkowski: no geometry
     assert bench.compulsory_bytes_per_zone_cycle(dict(prm, coords=problems.MINKOWSKI_CART)) == 320.0
     # Cartesian Kerr-Schild: every zone's connection and floor scales (42
-    # values) per substep, the metric evaluated in closed form in FP64; in
-    # mixed precision the whole centre table (64 values) and the three float
-    # face tables (22 values each)
+    # values) per substep, the metric evaluated in closed form; in mixed
+    # precision the three float face tables (22 values each) as well
     cks = dict(coords=problems.KERR_CKS, n3=168, precision=problems.FP64)
     assert bench.compulsory_bytes_per_zone_cycle(cks) == 320 + 2 * 42 * 8 == 992
-    assert bench.compulsory_bytes_per_zone_cycle(dict(cks, precision=problems.MIXED)) == 320 + 2 * (64 * 8 + 3 * 22 * 4)
+    assert bench.compulsory_bytes_per_zone_cycle(dict(cks, precision=problems.MIXED)) == 320 + 2 * (42 * 8 + 3 * 22 * 4)
 
 
 def test_split_design_bytes_count_the_face_fluxes():
