@@ -72,6 +72,22 @@ def test_cks_determinant_and_null_vector():
     assert np.abs(hh).max() < 1e-12 * np.abs(h).max() ** 2
 
 
+def test_cks_closed_form_inverse_and_lapse():
+    """Reading 17's closed forms, which the kernels evaluate instead of a
+    numerical inverse: with h = g - eta = f l l and l null, g^-1 = eta - eta h eta
+    and the lapse is 1/sqrt(1 + f), f = h_tt (l_t = 1). Checked against the
+    oracle's numerical inverse and lapse at the centres and at all faces."""
+    prm, _ = problems.cks_bondi(6, 5, 4)
+    grid = oracle.Grid(prm)
+    eta = np.diag([-1.0, 1.0, 1.0, 1.0])
+    for geo in (grid.cent, grid.face[1], grid.face[2], grid.face[3]):
+        g = geo["gcov"]
+        h = g - eta[:, :, None, None, None]
+        closed = eta[:, :, None, None, None] - np.einsum("am,mn...,nb->ab...", eta, h, eta)
+        assert np.abs(closed - geo["gcon"]).max() < 1e-13 * np.abs(geo["gcon"]).max()
+        assert np.abs(1.0 / np.sqrt(1.0 + h[0, 0]) - geo["alpha"]).max() < 1e-14
+
+
 def test_cks_connection_is_metric_compatible():
     prm, _ = problems.cks_bondi(6, 5, 4, a=A)
     grid = oracle.Grid(prm)
