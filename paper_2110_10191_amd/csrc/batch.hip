@@ -194,8 +194,14 @@ int configure(grmhd_batch* b, double* const* P, double* const* E, const int32_t*
       }
   b->electrons = electrons;
   if (na == 0) return GRMHD_OK;
-  BHIP(b, hipMemcpy(b->d_jobs, jobs.data(), sizeof(JobDesc) * na, hipMemcpyHostToDevice), "upload jobs");
-  BHIP(b, hipMemcpy(b->d_offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice), "upload offsets");
+  // on the batch's stream, which may be a non-blocking one: a copy on the
+  // null stream is not ordered before the graph launched on it, and a copy
+  // from pageable memory may return before its data has landed
+  BHIP(b, hipMemcpyAsync(b->d_jobs, jobs.data(), sizeof(JobDesc) * na, hipMemcpyHostToDevice, b->stream),
+       "upload jobs");
+  BHIP(b, hipMemcpyAsync(b->d_offs, offs.data(), sizeof(int) * offs.size(), hipMemcpyHostToDevice, b->stream),
+       "upload offsets");
+  BHIP(b, hipStreamSynchronize(b->stream), "synchronize");
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal), "begin capture");
   const bool prof_on = b->prof.on;
   b->prof.on = false;
@@ -279,8 +285,13 @@ int grmhd_batch_create(grmhd_ctx* const* jobs, int32_t n, void* hip_stream, grmh
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_offs, sizeof(int) * PH_COUNT * (n + 1));
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_dt, sizeof(double) * n);
   if (e == hipSuccess) e = hipMalloc((void**)&b->d_status, sizeof(int) * n);
-  if (e == hipSuccess) e = hipMemset(b->d_status, 0, sizeof(int) * n);
-  if (e == hipSuccess) e = hipMemset(b->d_dt, 0, sizeof(double) * n);
+  // cleared on the batch's stream, so that the clear is ordered before the
+  // step sizes grmhd_batch_set_dt copies in on the same stream (a null-stream
+  // memset is not ordered with a non-blocking stream and could land after
+  // them, leaving a job a zero step)
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_status, 0, sizeof(int) * n, b->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_dt, 0, sizeof(double) * n, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) {
     std::string m = std::string("batch set-up: ") + hipGetErrorString(e);
     grmhd_batch_free(b);

@@ -189,3 +189,21 @@ def test_cartesian_kerr_schild_validation(lib, edit, needle):
     with pytest.raises(lib.GrmhdError):
         lib.grmhd_context_bytes(prm)
     assert needle in lib.grmhd_last_error(None)
+
+
+def test_device_copies_and_clears_are_stream_ordered():
+    """Every copy and clear of device memory in the library is enqueued on a
+    context's or batch's stream (the stream may be a caller's non-blocking
+    one): a null-stream hipMemcpy / hipMemset is not ordered with such a
+    stream, and a batch's step sizes cleared that way could land after the
+    ones grmhd_batch_set_dt copies in."""
+    import glob
+    import re
+    csrc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2110_10191_amd", "csrc")
+    offenders = []
+    for path in sorted(glob.glob(os.path.join(csrc, "*.hip"))):
+        for n, line in enumerate(open(path), 1):
+            code = line.split("//")[0]
+            if re.search(r"\bhip(Memcpy|Memset)\s*\(", code):
+                offenders.append(f"{os.path.basename(path)}:{n}")
+    assert offenders == []
