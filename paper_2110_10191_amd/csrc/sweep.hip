@@ -234,7 +234,7 @@ hipError_t launch_geo(const Dims& d, const Tables& t, const CksBox& box, double 
 }
 
 // Cartesian Kerr-Schild in FP64 computes its face geometry instead of
-// streaming the 3D face tables (a third of the bytes the pass moves); the
+// streaming the 3D face tables (most of the bytes the pass moved); the
 // FP32 pass reads the float tables, cheaper than evaluating the metric in
 // FP64; the other coordinates read their 2D tables
 template <int RECON, typename T>
