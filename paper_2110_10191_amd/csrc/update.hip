@@ -272,7 +272,9 @@ __device__ void update_body(const Dims& d, const double* __restrict__ cent, cons
 // (256, 3): at least three waves per SIMD, i.e. at most 168 registers a lane.
 // Left free the compiler takes 224 (two waves) and the kernel waits on its
 // loads and long dependency chains with too little to switch to; the FP64
-// variant fits 168 without spilling.
+// variant fits 168 without spilling (the Cartesian Kerr-Schild variants,
+// which evaluate the metric, spill 4 registers and still gain: their loads
+// are the bound).
 template <typename TF, bool DEV_DT, bool CKS = false>
 __global__ __launch_bounds__(256, 3) void update_kernel(Dims d, const double* __restrict__ cent, CksBox box, UpdateParams up,
                                                      const TF* __restrict__ F1, const TF* __restrict__ F2,
