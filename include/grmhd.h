@@ -302,7 +302,7 @@ GRMHD_API int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_m
  * x2, one thread per zone (the face-flux kernel computes up to the three
  * lower faces of its zone); tx a power of two in [16, 256], tx * ty a multiple
  * of 64 and at most 512 (sweeps) or 256 (update). Defaults: sweeps 64 x 8,
- * update 64 x 4. Results do not depend on the tile. A batch uses the tiles of
+ * update 64 x 1. Results do not depend on the tile. A batch uses the tiles of
  * its first job for every job. Errors: EINVAL. */
 enum { GRMHD_TILE_SWEEP = 0, GRMHD_TILE_UPDATE = 1 };
 GRMHD_API int grmhd_set_tiles(grmhd_ctx *ctx, int32_t which, int32_t tx, int32_t ty);

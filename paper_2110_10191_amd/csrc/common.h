@@ -309,10 +309,10 @@ __device__ inline float weno5_edge(float x1, float x2, float x3, float x4, float
 // refetching them once per x3 plane.
 
 constexpr int NXCD = 8;
-constexpr int TILE_X = 64;   // default tiles: face fluxes 64 x 8 (512 threads), update 64 x 4
+constexpr int TILE_X = 64;   // default tiles: face fluxes 64 x 8 (512 threads), update 64 x 1
 constexpr int SWEEP_TILE_X = 64;
 constexpr int SWEEP_TILE_Y = 8;
-constexpr int TILE_Y = 4;
+constexpr int TILE_Y = 1;
 constexpr int SWEEP_MAX_THREADS = 512;   // launch bounds of the sweep kernels
 constexpr int UPDATE_MAX_THREADS = 256;  // launch bounds of the update and fixup kernels
 

@@ -34,7 +34,7 @@ from . import _binding as B
 WIDTHS = (32, 64, 128, 256)
 ROWS = (1, 2, 4, 8, 16)
 MAX_THREADS = {"sweep": 512, "update": 256}   # the kernels' launch bounds
-DEFAULT = {"sweep": (64, 8), "update": (64, 4)}
+DEFAULT = {"sweep": (64, 8), "update": (64, 1)}
 
 SWEEP_CLASSES = ("sweeps",)
 UPDATE_CLASSES = ("update", "fixup")
@@ -175,17 +175,24 @@ def tune_sim(sim, P, steps=3, repeats=3):
     """Time every candidate tile for the sweep and the update classes, each
     starting from state P (restored afterwards), and return
     ({"sweep": t, "update": t}, {"sweep": ms, "update": ms}). Leaves the best
-    tiles set on ``sim``."""
+    tiles set on ``sim``. Every candidate runs one untimed step first, and the
+    repeats go round all candidates in turn, so neither warm-up nor drift of
+    the device favours the candidates timed first."""
     P0 = P.clone()
     dt = sim.get_dt(P)
-    sim.step(P, dt, want_dt_next=False)          # warm the code objects and caches
     result, timings = {}, {}
     for cls, classes in (("sweep", SWEEP_CLASSES), ("update", UPDATE_CLASSES)):
-        times = {}
-        for tile in _ordered(cls):
+        order = _ordered(cls)
+        times = {tile: [] for tile in order}
+        for tile in order:
             sim.set_tiles(cls, *tile)
             P.copy_(P0)
-            times[tile] = time_classes(sim, P, dt, classes, steps, repeats)
+            sim.step(P, dt, want_dt_next=False)
+        for _ in range(repeats):
+            for tile in order:
+                sim.set_tiles(cls, *tile)
+                P.copy_(P0)
+                times[tile] += time_classes(sim, P, dt, classes, steps, 1)
         best, best_ms = pick(times)
         sim.set_tiles(cls, *best)
         result[cls] = best
@@ -205,10 +212,12 @@ def search(measure, repeats=3):
     tiles = dict(DEFAULT)
     best_t = {}
     for cls in ("sweep", "update"):
-        times = {}
-        for tile in _ordered(cls):
-            trial = dict(tiles, **{cls: tile})
-            times[tile] = [measure(trial) for _ in range(repeats)]
+        order = _ordered(cls)
+        times = {tile: [] for tile in order}
+        # the repeats go round all candidates in turn (no drift favours the first)
+        for _ in range(repeats):
+            for tile in order:
+                times[tile].append(measure(dict(tiles, **{cls: tile})))
         tiles[cls], best_t[cls] = pick(times)
     return tiles, best_t
 

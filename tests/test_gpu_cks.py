@@ -5,7 +5,7 @@ change of coordinates or of the stationary background), so the geometry tables
 are 3D and the x3 faces have a table of their own. The workload is a
 magnetised Michel flow on a box off the hole with a = 0.9375, Dirichlet
 boundaries on all six sides and floors on. The box is 40 x 28 x 20: the
-face-flux tile is 64 x 8 and the update tile 64 x 4, so both leave ragged
+face-flux tile is 64 x 8 and the update tile 64 x 1, so x1 leaves ragged
 tails.
 
 * FP64, MC and WENO5, stepped by grmhd_run from the oracle's first Courant

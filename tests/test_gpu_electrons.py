@@ -3,7 +3,7 @@ ABI) with the oracle's electron step.
 
 Bar as for the fluid step: relative L1 per variable <= 1e-10 after the steps
 (FP64), <= 1e-5 in mixed precision, both sides driven by the oracle's
-time-step sequence. Sizes span several 64 x 4 tiles with ragged tails."""
+time-step sequence. Sizes span several tiles with ragged tails."""
 
 import numpy as np
 import pytest

@@ -3,7 +3,7 @@
 Bar (FP64): relative L1 per primitive <= 1e-10 after 10 steps, with both sides
 driven by the oracle's time-step sequence; pointwise calls to ~1e-13. Mixed
 precision: relative L1 <= 1e-5 against the FP64 oracle. Sizes span several
-64 x 4 thread tiles with ragged tails; the full-size torus is checked on x3
+the default thread tiles (face fluxes 64 x 8, update 64 x 1) with ragged tails; the full-size torus is checked on x3
 slabs the oracle computes from a window.
 """
 

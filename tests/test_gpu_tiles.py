@@ -49,7 +49,7 @@ def test_tile_validation(lib):
     prm, _ = problems.linear_modes(n=8)
     sim = lib.Sim(prm)
     assert sim.get_tiles("sweep") == (64, 8)
-    assert sim.get_tiles("update") == (64, 4)
+    assert sim.get_tiles("update") == (64, 1)
     for bad in [(48, 4), (32, 3), (512, 1), (8, 8), (16, 3), (0, 4), (64, 0), (64, 16)]:
         with pytest.raises(lib.GrmhdError):
             sim.set_tiles("sweep", *bad)

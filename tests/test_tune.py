@@ -106,4 +106,4 @@ def test_search_finds_the_separable_minimum():
     assert best == {"sweep": 3.0, "update": 1.5}
     assert len(calls) == 2 * (len(tune.candidates("sweep")) + len(tune.candidates("update")))
     # the defaults are tried first
-    assert calls[0] == {"sweep": (64, 8), "update": (64, 4)}
+    assert calls[0] == {"sweep": (64, 8), "update": (64, 1)}
