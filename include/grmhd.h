@@ -295,6 +295,13 @@ enum {
   GRMHD_K_UPDATE = 4, GRMHD_K_FIXUP = 5, GRMHD_K_ELECTRONS = 6, GRMHD_K_COUNT = 7
 };
 GRMHD_API int grmhd_profile(grmhd_ctx *ctx, int32_t enable);
+/* Which kernel classes grmhd_profile brackets: mask is a set of bits
+ * (1 << GRMHD_K_*); the launches of the other classes run without events (each
+ * event record costs the stream a few microseconds, so a measurement that
+ * needs only some classes times those alone). Default: every class. Takes
+ * effect for launches enqueued after the call; the record is not cleared.
+ * Errors: EINVAL (null context, empty mask or a bit outside the classes). */
+GRMHD_API int grmhd_profile_kernels(grmhd_ctx *ctx, int32_t mask);
 GRMHD_API int grmhd_profile_read(grmhd_ctx *ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
 /* Thread-block tile of the face-flux kernel (GRMHD_TILE_SWEEP) or of the

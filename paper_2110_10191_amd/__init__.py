@@ -18,7 +18,7 @@ from ._binding import (  # noqa: F401
     grmhd_init, grmhd_free, grmhd_state_layout, grmhd_prim_to_cons, grmhd_cons_to_prim,
     grmhd_get_dt, grmhd_step, grmhd_step_electrons, grmhd_run_electrons, grmhd_run, grmhd_fill_ghosts, grmhd_substep, grmhd_update, grmhd_fixup, grmhd_speeds, grmhd_courant_dt,
     grmhd_divb, grmhd_divb_noalloc, grmhd_step_failures, grmhd_strerror,
-    grmhd_last_error, grmhd_version, grmhd_profile, grmhd_profile_read, KERNELS, Sim,
+    grmhd_last_error, grmhd_version, grmhd_profile, grmhd_profile_kernels, grmhd_profile_read, KERNELS, Sim,
     grmhd_set_tiles, grmhd_get_tiles, TILES, grmhd_context_bytes,
     grmhd_batch_create, grmhd_batch_set_dt, grmhd_batch_get, grmhd_batch_step, grmhd_batch_step_electrons,
     grmhd_batch_free,

@@ -15,7 +15,7 @@ GRMHD_OPT_FLOORS, GRMHD_OPT_FIXUP = 1, 2
 EXPORTED = [
     "grmhd_init", "grmhd_context_bytes", "grmhd_free", "grmhd_state_layout", "grmhd_prim_to_cons", "grmhd_cons_to_prim",
     "grmhd_get_dt", "grmhd_step", "grmhd_step_electrons", "grmhd_run_electrons", "grmhd_run", "grmhd_fill_ghosts", "grmhd_substep", "grmhd_update", "grmhd_fixup", "grmhd_speeds", "grmhd_courant_dt", "grmhd_divb", "grmhd_divb_noalloc", "grmhd_step_failures", "grmhd_strerror",
-    "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_read",
+    "grmhd_last_error", "grmhd_version", "grmhd_profile", "grmhd_profile_kernels", "grmhd_profile_read",
     "grmhd_set_tiles", "grmhd_get_tiles", "grmhd_batch_create", "grmhd_batch_set_dt", "grmhd_batch_get", "grmhd_batch_step", "grmhd_batch_step_electrons",
     "grmhd_batch_free", "grmhd_batch_last_error", "grmhd_batch_profile", "grmhd_batch_profile_read",
 ]
@@ -97,6 +97,7 @@ def _load():
         "grmhd_last_error": ([vp], ctypes.c_char_p),
         "grmhd_version": ([], ctypes.c_int),
         "grmhd_profile": ([vp, i32], ctypes.c_int),
+        "grmhd_profile_kernels": ([vp, i32], ctypes.c_int),
         "grmhd_profile_read": ([vp, i32, dp, ctypes.POINTER(i64)], ctypes.c_int),
         "grmhd_set_tiles": ([vp, i32, i32, i32], ctypes.c_int),
         "grmhd_get_tiles": ([vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)], ctypes.c_int),
@@ -286,6 +287,14 @@ def grmhd_version():
 
 def grmhd_profile(ctx, enable):
     _check(lib.grmhd_profile(ctx, 1 if enable else 0), ctx)
+
+
+def grmhd_profile_kernels(ctx, kernels):
+    """Bracket only these kernel classes (names or ids) while profiling is on."""
+    mask = 0
+    for k in kernels:
+        mask |= 1 << (KERNELS[k] if isinstance(k, str) else int(k))
+    _check(lib.grmhd_profile_kernels(ctx, mask), ctx)
 
 
 def grmhd_profile_read(ctx, kernel):

@@ -490,6 +490,14 @@ int grmhd_profile(grmhd_ctx* ctx, int32_t enable) {
   return GRMHD_OK;
 }
 
+int grmhd_profile_kernels(grmhd_ctx* ctx, int32_t mask) {
+  if (!ctx) return GRMHD_EINVAL;
+  if (mask <= 0 || (mask & ~((1 << GRMHD_K_COUNT) - 1)))
+    return fail(ctx, GRMHD_EINVAL, "profile_kernels: mask must be a non-empty set of GRMHD_K_* bits");
+  ctx->prof.mask = (unsigned)mask;
+  return GRMHD_OK;
+}
+
 int grmhd_profile_read(grmhd_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches) {
   if (!ctx || !total_ms || !launches) return GRMHD_EINVAL;
   if (kernel < 0 || kernel >= GRMHD_K_COUNT) return fail(ctx, GRMHD_EINVAL, "profile_read: unknown kernel");

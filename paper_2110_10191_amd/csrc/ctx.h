@@ -15,6 +15,7 @@ struct ProfRecord {
 // events of cleared records kept for reuse.
 struct Profiler {
   bool on = false;
+  unsigned mask = ~0u;  // kernel classes bracketed while on (bit GRMHD_K_*)
   std::vector<ProfRecord> rec;
   std::vector<hipEvent_t> pool;
 
@@ -64,7 +65,8 @@ struct ProfScope {
   hipStream_t s;
   ProfRecord r{};
   bool on;
-  ProfScope(Profiler& prof, hipStream_t stream, int kernel) : p(prof), s(stream), on(prof.on) {
+  ProfScope(Profiler& prof, hipStream_t stream, int kernel)
+      : p(prof), s(stream), on(prof.on && ((prof.mask >> kernel) & 1u)) {
     if (!on) return;
     r.kernel = kernel;
     r.start = p.event();

@@ -143,6 +143,7 @@ def test_null_context_calls_are_rejected(lib):
     assert lib.lib.grmhd_set_tiles(None, 0, 64, 4) == lib.GRMHD_EINVAL
     assert lib.lib.grmhd_get_tiles(None, 0, ctypes.byref(tx), ctypes.byref(ty)) == lib.GRMHD_EINVAL
     assert lib.lib.grmhd_profile(None, 1) == lib.GRMHD_EINVAL
+    assert lib.lib.grmhd_profile_kernels(None, 2) == lib.GRMHD_EINVAL
     assert lib.lib.grmhd_step(None, None, 0.1, None) == lib.GRMHD_EINVAL
 
 
