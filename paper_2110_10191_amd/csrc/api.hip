@@ -158,18 +158,23 @@ struct ElectronPass {
 // el: also advect and heat the electron entropies.
 // flags: the failure flags the update writes (the context's own when null);
 // fix: run the fixup (with the context's flags and no halo sides) as well.
+// extra_reset: further counters to clear first (8: the step's totals);
+// dtr: first set the device step size from the previous step's counters.
 int substep(grmhd_ctx* c, double* Ps, double* Pb, double* Pout, double dt, bool want_ctop,
             const double* dt_dev = nullptr, double dt_scale = 1.0, bool fill = true,
-            const ElectronPass* el = nullptr, int8_t* flags = nullptr, bool fix = true) {
+            const ElectronPass* el = nullptr, int8_t* flags = nullptr, bool fix = true, int extra_reset = 0,
+            const DtRule* dtr = nullptr) {
   int8_t* fl = flags ? flags : c->flags;
   hipStream_t s = c->stream;
   // the counters the face fluxes and the update count into start at zero (the
   // ghost fill clears them when there is one)
-  const int reset_mask = want_ctop ? (1 | 4) : 4;
+  const int reset_mask = (want_ctop ? (1 | 4) : 4) | extra_reset;
   if (fill) {
     ProfScope ps(c->prof, s, GRMHD_K_GHOSTS);
-    HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s, c->ctr, reset_mask), "ghost fill");
+    HIP_OR_FAIL(c, launch_fill_ghosts(c->p, c->d, c->t, Ps, Pb, s, c->ctr, reset_mask, dtr ? *dtr : DtRule{}),
+                "ghost fill");
   } else {
+    if (dtr) HIP_OR_FAIL(c, launch_ctx_dt(c->ctr, dtr->cfl, dtr->dx[0], dtr->dx[1], dtr->dx[2], s), "dt");
     HIP_OR_FAIL(c, launch_reset(c->ctr, reset_mask, s), "reset");
   }
   if (el) {
@@ -280,14 +285,19 @@ int run_steps(grmhd_ctx* ctx, double* P, double* E, int32_t model, double fel, i
   const double* dtp = &ctx->ctr->dt;
   const ElectronPass pred{E, E, ctx->Eh, model, fel};
   const ElectronPass corr{ctx->Eh, E, E, model, fel};
+  // each step's predictor ghost fill first takes the step size from the
+  // previous step's counters (the host's dt for the first step), then clears
+  // the step's totals; the last step's rule runs after the loop
+  const DtRule rule{1, ctx->p.cfl, {ctx->dx[0], ctx->dx[1], ctx->dx[2]}};
   for (int s = 0; s < nsteps; ++s) {
-    HIP_OR_FAIL(ctx, launch_reset(ctx->ctr, 8, ctx->stream), "reset");
-    int st = substep(ctx, P, P, ctx->Ph, 0.0, false, dtp, 0.5, true, E ? &pred : nullptr);
+    int st = substep(ctx, P, P, ctx->Ph, 0.0, false, dtp, 0.5, true, E ? &pred : nullptr, nullptr, true, 8,
+                     s > 0 ? &rule : nullptr);
     if (st != GRMHD_OK) return st;
     st = substep(ctx, ctx->Ph, P, P, 0.0, true, dtp, 1.0, true, E ? &corr : nullptr);
     if (st != GRMHD_OK) return st;
-    HIP_OR_FAIL(ctx, launch_ctx_dt(ctx->ctr, ctx->p.cfl, ctx->dx[0], ctx->dx[1], ctx->dx[2], ctx->stream), "dt");
   }
+  if (nsteps > 0)
+    HIP_OR_FAIL(ctx, launch_ctx_dt(ctx->ctr, ctx->p.cfl, ctx->dx[0], ctx->dx[1], ctx->dx[2], ctx->stream), "dt");
   HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.dt, &ctx->ctr->dt, sizeof(double), hipMemcpyDeviceToHost, ctx->stream),
               "read dt");
   HIP_OR_FAIL(ctx, hipMemcpyAsync(&host.status, &ctx->ctr->status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream),

@@ -18,6 +18,8 @@
 namespace {
 
 __device__ void reset_counters(Counters* c, int mask);
+__device__ void device_dt(const unsigned long long* ctop, unsigned bad, const double* dx, double cfl, double* dt,
+                          int* status);
 
 constexpr int MAX_DEVICES = 64;  // devices the no-allocation scratch lookup keeps
 
@@ -150,12 +152,16 @@ __device__ void ghost_fill_body(const grmhd_problem& p, const Dims& d, const dou
 
 // ---- single-job kernels
 
-// all ghosts of a state in one launch; block 0 also clears the counters of
+// all ghosts of a state in one launch; block 0 also takes the step size from
+// the previous step's counters (dr.on) and then clears the counters of
 // reset_mask (the step's ghost fill comes before the kernels that count)
 __global__ __launch_bounds__(256) void ghost_fill_kernel(grmhd_problem p, Dims d, const double* __restrict__ cent,
                                                          double* P, const double* dsrc, Counters* ctr,
-                                                         int reset_mask) {
-  if (ctr && blockIdx.x == 0 && threadIdx.x == 0) reset_counters(ctr, reset_mask);
+                                                         int reset_mask, DtRule dr) {
+  if (ctr && blockIdx.x == 0 && threadIdx.x == 0) {
+    if (dr.on) device_dt(ctr->ctop, ctr->bad, dr.dx, dr.cfl, &ctr->dt, &ctr->status);
+    reset_counters(ctr, reset_mask);
+  }
   ghost_fill_body(p, d, cent, P, dsrc, (int)(blockIdx.x * blockDim.x + threadIdx.x));
 }
 
@@ -320,10 +326,10 @@ dim3 divb_grid(const Dims& d) { return dim3((d.n1 + 63) / 64, (d.n2 + 3) / 4, d.
 }  // namespace
 
 hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,
-                              const double* dsrc, hipStream_t s, Counters* ctr, int reset_mask) {
+                              const double* dsrc, hipStream_t s, Counters* ctr, int reset_mask, DtRule dt_rule) {
   const int n = ghost_threads(d);
   hipLaunchKernelGGL(ghost_fill_kernel, dim3((n + 255) / 256), dim3(256, 1, 1), 0, s, p, d, t.cent, P, dsrc, ctr,
-                     reset_mask);
+                     reset_mask, dt_rule);
   return hipGetLastError();
 }
 

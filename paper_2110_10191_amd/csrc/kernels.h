@@ -124,9 +124,19 @@ hipError_t launch_batch_dt(const BatchView& bv, hipStream_t s);
 
 hipError_t launch_geometry(const grmhd_problem& p, const Dims& d, const Tables& t, hipStream_t s);
 
+// the step-size rule dt <- min(cfl / sum_d(ctop_d / dx_d), 1.3 dt) on the
+// counters of the previous step (on = 0: not applied)
+struct DtRule {
+  int on;
+  double cfl;
+  double dx[3];
+};
+
+// with ctr: block 0 first applies dt_rule (when on) and then clears the
+// counters of reset_mask, before any kernel after the fill counts into them
 hipError_t launch_fill_ghosts(const grmhd_problem& p, const Dims& d, const Tables& t, double* P,
                               const double* dirichlet_src, hipStream_t s, Counters* ctr = nullptr,
-                              int reset_mask = 0);
+                              int reset_mask = 0, DtRule dt_rule = DtRule{});
 
 // face fluxes of all three directions of state P into F[0..2] (double for
 // fp64, float for mixed) with the problem's reconstruction and gamma;
