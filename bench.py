@@ -446,7 +446,8 @@ def main():
         driver synchronises the host with the device when it returns."""
         if args.path == "device":
             # grmhd_run(_electrons): the step size kept on the device (dt <-
-            # min(dt_next, 1.3 dt) by a one-thread kernel); one sync at the end
+            # min(dt_next, 1.3 dt), applied by the next step's first ghost-fill
+            # launch); one sync at the end
             if E is not None:
                 return sim.run_electrons(P, E, nsteps, dt, args.electrons)
             return sim.run(P, nsteps, dt)
