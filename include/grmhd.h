@@ -285,7 +285,8 @@ GRMHD_API int grmhd_step_failures(grmhd_ctx *ctx, int64_t *n_fail);
 /* Kernel timing for measurement. grmhd_profile(ctx, 1) clears the record and
  * starts bracketing every kernel launch of grmhd_step, grmhd_run and the
  * electron calls (GRMHD_K_ELECTRONS: the scalar ghosts, advection and
- * heating) with HIP events on the context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
+ * heating) of the classes chosen with grmhd_profile_kernels (default: all)
+ * with HIP events on the context stream; grmhd_profile(ctx, 0) stops. grmhd_profile_read returns, for
  * one kernel class, the summed device time in ms and the launch count since
  * the last clear; synchronises. Timing adds two event records per launch.
  * GRMHD_K_SWEEPS is the face-flux pass of all three directions, one launch per
