@@ -80,3 +80,16 @@ def test_arithmetic_ceiling_of_the_hbm_fraction():
     # the measured FP64 fraction: flops over the step time against the vector peak
     r = bench.arithmetic_ceiling(bench.FP64_PEAK * 1e-3, zones, per_zc, 4e-3)
     assert abs(r["step_fp64_frac"] - 0.25) < 1e-12
+
+
+def test_timed_kernel_classes_cover_the_dominant_candidates():
+    """Inside the timed region the bench brackets only TIMED_KERNELS with
+    events; the dominant kernel is chosen among the face fluxes and the update,
+    so both must be timed there, and every name must be a library class."""
+    import paper_2110_10191_amd as g
+    assert set(bench.TIMED_KERNELS) == {"sweeps", "update"}
+    assert set(bench.TIMED_KERNELS) <= set(g.KERNELS)
+    mask = 0
+    for name in bench.TIMED_KERNELS:
+        mask |= 1 << g.KERNELS[name]
+    assert 0 < mask < 1 << (max(g.KERNELS.values()) + 1)
