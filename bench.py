@@ -483,9 +483,10 @@ def main():
     kernels = {name: g.grmhd_profile_read(sim.ctx, name) for name in TIMED_KERNELS}
     # the remaining classes, every launch bracketed, outside the timed region
     others = [name for name in g.KERNELS if name not in TIMED_KERNELS]
+    other_steps = min(args.steps, 5)
     g.grmhd_profile_kernels(sim.ctx, others)
     g.grmhd_profile(sim.ctx, True)
-    dt = advance(min(args.steps, 5), dt)
+    dt = advance(other_steps, dt)
     g.grmhd_profile(sim.ctx, False)
     g.grmhd_profile_kernels(sim.ctx, list(g.KERNELS))
     kernels.update({name: g.grmhd_profile_read(sim.ctx, name) for name in others})
@@ -577,7 +578,8 @@ def main():
         # new primitives and U_K and writes both entropies
         fb = 4 if mixed else 8
         per_zone = 2 * ((4 + 2 + 2 + 2) * 8 + 3 * fb + (8 + 2 + 2) * 8)
-        e_ms = kernels["electrons"][0] / args.steps
+        # the electron classes are timed in the pass after the timed region
+        e_ms = kernels["electrons"][0] / other_steps
         roofline["electron_passes"] = {"ms_per_step": e_ms, "algorithmic_bytes_per_zone_cycle": per_zone,
                                        "achieved_GBps": per_zone * zones / (e_ms / 1e3) / 1e9,
                                        "frac": per_zone * zones / (e_ms / 1e3) / HBM_PEAK}
